@@ -1,0 +1,1027 @@
+/*
+ * fpo.c -- plain FP64 CPU oracle of the free-stream-preserving conservative
+ * finite-difference scheme with reformulated upwind dissipation (Su, Cai,
+ * Pan, Hu).  TEST INFRASTRUCTURE ONLY: see fpo.h.
+ *
+ * Every function follows the paper's definitions in the paper's order and
+ * notation, one node or face at a time, with no blocking, fusion or
+ * reordering.  Where the paper is silent the readings used are stated next to
+ * the code (tangent basis, Roe states, local Lax-Friedrichs speeds, face
+ * interpolation order, 2D metrics).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#include "fpo.h"
+
+#define NVMAX 5
+
+/* ------------------------------------------------------------------------ */
+/* array layout                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int ndim, nv, nmet, g;
+    int n[3];   /* interior nodes (n[2] = 1 in 2D) */
+    int N[3];   /* stored nodes per axis (N[2] = 1 in 2D) */
+    int gk;     /* ghost offset along k (0 in 2D) */
+    long vol;   /* nodes per variable */
+    int bc[3];
+} layout;
+
+static int make_layout(const fpo_grid *gr, layout *L)
+{
+    if (!gr || (gr->ndim != 2 && gr->ndim != 3) || gr->g < 3 || gr->g > 8)
+        return -1;
+    L->ndim = gr->ndim;
+    L->nv = gr->ndim + 2;
+    L->nmet = gr->ndim == 3 ? 10 : 5;
+    L->g = gr->g;
+    for (int d = 0; d < 3; d++) {
+        L->n[d] = gr->n[d];
+        L->bc[d] = gr->bc[d];
+    }
+    if (gr->ndim == 2) {
+        L->n[2] = 1;
+        L->bc[2] = 0;
+    }
+    for (int d = 0; d < gr->ndim; d++) {
+        if (L->n[d] < 1 || (L->bc[d] != 0 && L->bc[d] != 1))
+            return -1;
+        /* a periodic axis must hold at least as many nodes as one ghost layer */
+        if (L->bc[d] == 0 && L->n[d] < L->g)
+            return -1;
+        L->N[d] = L->n[d] + 2 * L->g;
+    }
+    if (gr->ndim == 2) {
+        L->N[2] = 1;
+        L->gk = 0;
+    } else {
+        L->gk = L->g;
+    }
+    L->vol = (long)L->N[0] * L->N[1] * L->N[2];
+    return 0;
+}
+
+/* offset of node (i, j, k), indices relative to the first interior node */
+static long at(const layout *L, int i, int j, int k)
+{
+    return ((long)(k + L->gk) * L->N[1] + (j + L->g)) * L->N[0] + (i + L->g);
+}
+
+/* ------------------------------------------------------------------------ */
+/* central face interpolation I_Y and derivative D_Y, eq. (metric_discret)   */
+/* ------------------------------------------------------------------------ */
+
+/* w[0 .. Y-1] hold nodes i-Y/2+1 .. i+Y/2; returns the value at face i+1/2 */
+double fpo_face_interp(int Y, const double *w)
+{
+    switch (Y) {
+    case 2:
+        return (w[0] + w[1]) / 2.0;
+    case 4:
+        return (-w[0] + 7.0 * w[1] + 7.0 * w[2] - w[3]) / 12.0;
+    case 6:
+        return (w[0] - 8.0 * w[1] + 37.0 * w[2] + 37.0 * w[3] - 8.0 * w[4] + w[5]) / 60.0;
+    case 8:
+        return (-3.0 * w[0] + 29.0 * w[1] - 139.0 * w[2] + 533.0 * w[3] + 533.0 * w[4]
+                - 139.0 * w[5] + 29.0 * w[6] - 3.0 * w[7]) / 840.0;
+    }
+    return NAN;
+}
+
+/* D_Y at node i from samples w[0 .. Y] = nodes i-Y/2 .. i+Y/2:
+ * (x_xi)_i = x_{i+1/2} - x_{i-1/2} */
+static double deriv_Y(int Y, const double *w)
+{
+    return fpo_face_interp(Y, w + 1) - fpo_face_interp(Y, w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* symmetric conservative metrics, eqs. (JBabc) and (JB)                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const double *xyz;
+    int ndim, Y, gc;
+    int Nc[3];
+    long volc;
+} cgrid;
+
+enum { XI = 0, ETA = 1, ZETA = 2 };
+enum { CX = 0, CY = 1, CZ = 2 };
+
+static double crd(const cgrid *C, int c, const int p[3])
+{
+    long off;
+    if (C->ndim == 2)
+        off = (long)(p[1] + C->gc) * C->Nc[0] + (p[0] + C->gc);
+    else
+        off = ((long)(p[2] + C->gc) * C->Nc[1] + (p[1] + C->gc)) * C->Nc[0] + (p[0] + C->gc);
+    return C->xyz[c * C->volc + off];
+}
+
+/* derivative of coordinate c along computational axis e at node p */
+static double dcrd(const cgrid *C, int c, int e, const int p[3])
+{
+    double w[9];
+    int h = C->Y / 2, q[3] = {p[0], p[1], p[2]};
+    for (int m = -h; m <= h; m++) {
+        q[e] = p[e] + m;
+        w[m + h] = crd(C, c, q);
+    }
+    return deriv_Y(C->Y, w);
+}
+
+/* T(a, e, b, f) = ( a_e * b )_f : derivative along f of (D_e a) times b */
+static double T(const cgrid *C, int a, int e, int b, int f, const int p[3])
+{
+    double w[9];
+    int h = C->Y / 2, q[3] = {p[0], p[1], p[2]};
+    for (int m = -h; m <= h; m++) {
+        q[f] = p[f] + m;
+        w[m + h] = dcrd(C, a, e, q) * crd(C, b, q);
+    }
+    return deriv_Y(C->Y, w);
+}
+
+/* the nine metrics s_{d,c} = (d_c)/J of eq. (JBabc) at node p (3D), written
+ * term by term as printed: e.g. xi_x/J = 1/2[(y_eta z)_zeta - (y_zeta z)_eta
+ * + (y z_zeta)_eta - (y z_eta)_zeta] */
+static void scmm3(const cgrid *C, const int p[3], double s[9])
+{
+    /* xi_x/J */
+    s[0] = 0.5 * (T(C, CY, ETA, CZ, ZETA, p) - T(C, CY, ZETA, CZ, ETA, p)
+                  + T(C, CZ, ZETA, CY, ETA, p) - T(C, CZ, ETA, CY, ZETA, p));
+    /* xi_y/J = 1/2[(x z_eta)_zeta - (x z_zeta)_eta + (x_zeta z)_eta - (x_eta z)_zeta] */
+    s[1] = 0.5 * (T(C, CZ, ETA, CX, ZETA, p) - T(C, CZ, ZETA, CX, ETA, p)
+                  + T(C, CX, ZETA, CZ, ETA, p) - T(C, CX, ETA, CZ, ZETA, p));
+    /* xi_z/J = 1/2[(x_eta y)_zeta - (x_zeta y)_eta + (x y_zeta)_eta - (x y_eta)_zeta] */
+    s[2] = 0.5 * (T(C, CX, ETA, CY, ZETA, p) - T(C, CX, ZETA, CY, ETA, p)
+                  + T(C, CY, ZETA, CX, ETA, p) - T(C, CY, ETA, CX, ZETA, p));
+    /* eta_x/J = 1/2[(y_zeta z)_xi - (y_xi z)_zeta + (y z_xi)_zeta - (y z_zeta)_xi] */
+    s[3] = 0.5 * (T(C, CY, ZETA, CZ, XI, p) - T(C, CY, XI, CZ, ZETA, p)
+                  + T(C, CZ, XI, CY, ZETA, p) - T(C, CZ, ZETA, CY, XI, p));
+    /* eta_y/J = 1/2[(x z_zeta)_xi - (x z_xi)_zeta + (x_xi z)_zeta - (x_zeta z)_xi] */
+    s[4] = 0.5 * (T(C, CZ, ZETA, CX, XI, p) - T(C, CZ, XI, CX, ZETA, p)
+                  + T(C, CX, XI, CZ, ZETA, p) - T(C, CX, ZETA, CZ, XI, p));
+    /* eta_z/J = 1/2[(x_zeta y)_xi - (x_xi y)_zeta + (x y_xi)_zeta - (x y_zeta)_xi] */
+    s[5] = 0.5 * (T(C, CX, ZETA, CY, XI, p) - T(C, CX, XI, CY, ZETA, p)
+                  + T(C, CY, XI, CX, ZETA, p) - T(C, CY, ZETA, CX, XI, p));
+    /* zeta_x/J = 1/2[(y_xi z)_eta - (y_eta z)_xi + (y z_eta)_xi - (y z_xi)_eta] */
+    s[6] = 0.5 * (T(C, CY, XI, CZ, ETA, p) - T(C, CY, ETA, CZ, XI, p)
+                  + T(C, CZ, ETA, CY, XI, p) - T(C, CZ, XI, CY, ETA, p));
+    /* zeta_y/J = 1/2[(x z_xi)_eta - (x z_eta)_xi + (x_eta z)_xi - (x_xi z)_eta] */
+    s[7] = 0.5 * (T(C, CZ, XI, CX, ETA, p) - T(C, CZ, ETA, CX, XI, p)
+                  + T(C, CX, ETA, CZ, XI, p) - T(C, CX, XI, CZ, ETA, p));
+    /* zeta_z/J = 1/2[(x_xi y)_eta - (x_eta y)_xi + (x y_eta)_xi - (x y_xi)_eta] */
+    s[8] = 0.5 * (T(C, CX, XI, CY, ETA, p) - T(C, CX, ETA, CY, XI, p)
+                  + T(C, CY, ETA, CX, XI, p) - T(C, CY, XI, CX, ETA, p));
+}
+
+/* 2D reduction of eq. (JBabc) (z = zeta, nothing depends on zeta):
+ * xi_x/J = y_eta, xi_y/J = -x_eta, eta_x/J = -y_xi, eta_y/J = x_xi */
+static void scmm2(const cgrid *C, const int p[3], double s[4])
+{
+    s[0] = dcrd(C, CY, ETA, p);
+    s[1] = -dcrd(C, CX, ETA, p);
+    s[2] = -dcrd(C, CY, XI, p);
+    s[3] = dcrd(C, CX, XI, p);
+}
+
+/* 1/J of eq. (JB): 1/3 sum_d ( x s_{d,x} + y s_{d,y} + z s_{d,z} )_d (3D);
+ * in 2D the same construction with z = zeta reduces to
+ * 1/2 [ (x y_eta - y x_eta)_xi + (y x_xi - x y_xi)_eta ]. */
+static double jacobian_inv(const cgrid *C, const int p[3])
+{
+    double w[9];
+    int h = C->Y / 2;
+    if (C->ndim == 3) {
+        double sum = 0.0;
+        for (int d = 0; d < 3; d++) {
+            int q[3] = {p[0], p[1], p[2]};
+            for (int m = -h; m <= h; m++) {
+                double s[9];
+                q[d] = p[d] + m;
+                scmm3(C, q, s);
+                w[m + h] = crd(C, CX, q) * s[3 * d + 0] + crd(C, CY, q) * s[3 * d + 1]
+                           + crd(C, CZ, q) * s[3 * d + 2];
+            }
+            sum += deriv_Y(C->Y, w);
+        }
+        return sum / 3.0;
+    } else {
+        double a, b;
+        int q[3] = {p[0], p[1], p[2]};
+        for (int m = -h; m <= h; m++) {
+            q[0] = p[0] + m;
+            w[m + h] = crd(C, CX, q) * dcrd(C, CY, ETA, q) - crd(C, CY, q) * dcrd(C, CX, ETA, q);
+        }
+        a = deriv_Y(C->Y, w);
+        q[0] = p[0];
+        for (int m = -h; m <= h; m++) {
+            q[1] = p[1] + m;
+            w[m + h] = crd(C, CY, q) * dcrd(C, CX, XI, q) - crd(C, CX, q) * dcrd(C, CY, XI, q);
+        }
+        b = deriv_Y(C->Y, w);
+        return 0.5 * (a + b);
+    }
+}
+
+static void metrics_node(const cgrid *C, const int p[3], double *out /* nmet */)
+{
+    if (C->ndim == 3) {
+        scmm3(C, p, out);
+        out[9] = jacobian_inv(C, p);
+    } else {
+        scmm2(C, p, out);
+        out[4] = jacobian_inv(C, p);
+    }
+}
+
+static int make_cgrid(const layout *L, int Y, const double *xyz, cgrid *C)
+{
+    if (Y != 2 && Y != 4 && Y != 6 && Y != 8)
+        return -1;
+    if (L->g < Y / 2) /* the face interpolation I_Y reaches Y/2 nodes */
+        return -1;
+    C->xyz = xyz;
+    C->ndim = L->ndim;
+    C->Y = Y;
+    C->gc = L->g + Y / 2;
+    for (int d = 0; d < 3; d++)
+        C->Nc[d] = d < L->ndim ? L->n[d] + 2 * C->gc : 1;
+    C->volc = (long)C->Nc[0] * C->Nc[1] * C->Nc[2];
+    return 0;
+}
+
+int fpo_metrics(const fpo_grid *gr, int Y, const double *xyz, double *met)
+{
+    layout L;
+    cgrid C;
+    if (make_layout(gr, &L) || make_cgrid(&L, Y, xyz, &C) || !met)
+        return -1;
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; d++) {
+        if (d >= L.ndim) {
+            lo[d] = 0;
+            hi[d] = 1;
+        } else if (L.bc[d] == 0) { /* periodic: interior, then copy to ghosts */
+            lo[d] = 0;
+            hi[d] = L.n[d];
+        } else { /* frozen: computed on the ghost nodes from the coordinates */
+            lo[d] = -L.g;
+            hi[d] = L.n[d] + L.g;
+        }
+    }
+    memset(met, 0, sizeof(double) * L.nmet * L.vol);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = lo[2]; k < hi[2]; k++)
+        for (int j = lo[1]; j < hi[1]; j++)
+            for (int i = lo[0]; i < hi[0]; i++) {
+                int p[3] = {i, j, k};
+                double m[10];
+                metrics_node(&C, p, m);
+                for (int c = 0; c < L.nmet; c++)
+                    met[c * L.vol + at(&L, i, j, k)] = m[c];
+            }
+    /* periodic ghost layers hold exact copies of the periodic image */
+    for (int d = 0; d < L.ndim; d++) {
+        if (L.bc[d] != 0)
+            continue;
+        for (int k = (L.ndim == 3 ? -L.g : 0); k < (L.ndim == 3 ? L.n[2] + L.g : 1); k++)
+            for (int j = -L.g; j < L.n[1] + L.g; j++)
+                for (int i = -L.g; i < L.n[0] + L.g; i++) {
+                    int p[3] = {i, j, k};
+                    if (p[d] >= 0 && p[d] < L.n[d])
+                        continue;
+                    int src[3] = {i, j, k};
+                    src[d] = ((p[d] % L.n[d]) + L.n[d]) % L.n[d];
+                    for (int c = 0; c < L.nmet; c++)
+                        met[c * L.vol + at(&L, i, j, k)] =
+                            met[c * L.vol + at(&L, src[0], src[1], src[2])];
+                }
+    }
+    return 0;
+}
+
+int fpo_metrics_at(const fpo_grid *gr, int Y, const double *xyz, int npts,
+                   const int *ijk, double *out)
+{
+    layout L;
+    cgrid C;
+    if (make_layout(gr, &L) || make_cgrid(&L, Y, xyz, &C) || npts < 0)
+        return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int t = 0; t < npts; t++) {
+        int p[3] = {ijk[3 * t], ijk[3 * t + 1], L.ndim == 3 ? ijk[3 * t + 2] : 0};
+        metrics_node(&C, p, out + (long)L.nmet * t);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Euler fluxes, eqs. (F)-(H) and (EOS)                                     */
+/* ------------------------------------------------------------------------ */
+
+/* pressure from the conserved state: p = (gamma-1) rho e, e = E - |u|^2/2 */
+static double pressure(int ndim, double gam, const double *Q)
+{
+    double rho = Q[0], ke = 0.0;
+    for (int c = 0; c < ndim; c++)
+        ke += Q[1 + c] * Q[1 + c];
+    ke = 0.5 * ke / rho;
+    return (gam - 1.0) * (Q[ndim + 1] - ke);
+}
+
+/* physical fluxes F (x), G (y), H (z) of the state Q: Fx[c][v] */
+static void phys_flux(int ndim, double gam, const double *Q, double Fx[3][NVMAX])
+{
+    int nv = ndim + 2;
+    double rho = Q[0], p = pressure(ndim, gam, Q);
+    for (int c = 0; c < ndim; c++) {
+        double uc = Q[1 + c] / rho;
+        Fx[c][0] = Q[1 + c];                       /* rho u_c */
+        for (int a = 0; a < ndim; a++)             /* rho u_a u_c + p delta_ac */
+            Fx[c][1 + a] = Q[1 + a] * uc + (a == c ? p : 0.0);
+        Fx[c][nv - 1] = (Q[nv - 1] + p) * uc;      /* (rho E + p) u_c */
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* characteristic system of A = dF~/dQ~ at the face                          */
+/* ------------------------------------------------------------------------ */
+
+/* Roe average of the two nodes adjacent to the face; eigenvectors of the
+ * flux Jacobian along the unit normal n = s_f/|s_f|, eigenvalues scaled by
+ * sigma = |s_f| / (1/J)_f (A acts on Q~ = Q/J).  Degenerate eigenvectors use
+ * the tangent t1 = normalize(n x e_a) with a = argmin |n_k| (lowest k on
+ * ties) and t2 = n x t1; in 2D t = (-n_y, n_x).  Field order: u_n - c,
+ * u_n (entropy), tangential field(s), u_n + c. */
+typedef struct {
+    double R[NVMAX][NVMAX];  /* R[row][s]: column s is r_s */
+    double L[NVMAX][NVMAX];  /* L[s][col]: row s is l_s */
+    double lam[NVMAX];       /* Roe eigenvalues sigma*(u_n + kappa_s c) */
+    double n[3];
+    double sigma;
+} charsys;
+
+static void roe_system(int ndim, double gam, const double *QL, const double *QR,
+                       const double *sf, double Vf, charsys *S)
+{
+    int nv = ndim + 2;
+    double uL[3] = {0, 0, 0}, uR[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+    double pL = pressure(ndim, gam, QL), pR = pressure(ndim, gam, QR);
+    double HL = (QL[nv - 1] + pL) / QL[0], HR = (QR[nv - 1] + pR) / QR[0];
+    double wL = sqrt(QL[0]), wR = sqrt(QR[0]);
+    for (int c = 0; c < ndim; c++) {
+        uL[c] = QL[1 + c] / QL[0];
+        uR[c] = QR[1 + c] / QR[0];
+        u[c] = (wL * uL[c] + wR * uR[c]) / (wL + wR);
+    }
+    double H = (wL * HL + wR * HR) / (wL + wR);
+    double q2 = 0.0;
+    for (int c = 0; c < ndim; c++)
+        q2 += u[c] * u[c];
+    double cs = sqrt((gam - 1.0) * (H - 0.5 * q2));
+
+    double snorm = 0.0;
+    for (int c = 0; c < ndim; c++)
+        snorm += sf[c] * sf[c];
+    snorm = sqrt(snorm);
+    double n[3] = {0, 0, 0};
+    for (int c = 0; c < ndim; c++)
+        n[c] = sf[c] / snorm;
+    double un = 0.0;
+    for (int c = 0; c < ndim; c++)
+        un += n[c] * u[c];
+    S->sigma = snorm / Vf;
+    for (int c = 0; c < 3; c++)
+        S->n[c] = n[c];
+
+    double b2 = (gam - 1.0) / (cs * cs);
+    double b1 = 0.5 * b2 * q2;
+    memset(S->R, 0, sizeof S->R);
+    memset(S->L, 0, sizeof S->L);
+
+    int last = nv - 1;
+    /* acoustic fields s = 0 (u_n - c) and s = last (u_n + c), entropy s = 1 */
+    S->R[0][0] = 1.0;
+    S->R[0][1] = 1.0;
+    S->R[0][last] = 1.0;
+    for (int c = 0; c < ndim; c++) {
+        S->R[1 + c][0] = u[c] - cs * n[c];
+        S->R[1 + c][1] = u[c];
+        S->R[1 + c][last] = u[c] + cs * n[c];
+    }
+    S->R[last][0] = H - cs * un;
+    S->R[last][1] = 0.5 * q2;
+    S->R[last][last] = H + cs * un;
+
+    S->L[0][0] = 0.5 * (b1 + un / cs);
+    S->L[1][0] = 1.0 - b1;
+    S->L[last][0] = 0.5 * (b1 - un / cs);
+    for (int c = 0; c < ndim; c++) {
+        S->L[0][1 + c] = 0.5 * (-b2 * u[c] - n[c] / cs);
+        S->L[1][1 + c] = b2 * u[c];
+        S->L[last][1 + c] = 0.5 * (-b2 * u[c] + n[c] / cs);
+    }
+    S->L[0][last] = 0.5 * b2;
+    S->L[1][last] = -b2;
+    S->L[last][last] = 0.5 * b2;
+
+    /* tangential (shear) fields */
+    double t[2][3];
+    int nt;
+    if (ndim == 2) {
+        t[0][0] = -n[1];
+        t[0][1] = n[0];
+        t[0][2] = 0.0;
+        nt = 1;
+    } else {
+        int a = 0;
+        for (int c = 1; c < 3; c++)
+            if (fabs(n[c]) < fabs(n[a]))
+                a = c;
+        double e[3] = {0, 0, 0};
+        e[a] = 1.0;
+        double x[3] = {n[1] * e[2] - n[2] * e[1], n[2] * e[0] - n[0] * e[2],
+                       n[0] * e[1] - n[1] * e[0]};
+        double xn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        for (int c = 0; c < 3; c++)
+            t[0][c] = x[c] / xn;
+        t[1][0] = n[1] * t[0][2] - n[2] * t[0][1];
+        t[1][1] = n[2] * t[0][0] - n[0] * t[0][2];
+        t[1][2] = n[0] * t[0][1] - n[1] * t[0][0];
+        nt = 2;
+    }
+    for (int r = 0; r < nt; r++) {
+        int s = 2 + r;
+        double ut = 0.0;
+        for (int c = 0; c < ndim; c++)
+            ut += u[c] * t[r][c];
+        S->R[0][s] = 0.0;
+        for (int c = 0; c < ndim; c++)
+            S->R[1 + c][s] = t[r][c];
+        S->R[last][s] = ut;
+        S->L[s][0] = -ut;
+        for (int c = 0; c < ndim; c++)
+            S->L[s][1 + c] = t[r][c];
+        S->L[s][last] = 0.0;
+    }
+    for (int s = 0; s < nv; s++) {
+        double kap = s == 0 ? -1.0 : (s == last ? 1.0 : 0.0);
+        S->lam[s] = S->sigma * (un + kap * cs);
+    }
+}
+
+int fpo_eigensystem(int ndim, double gamma, const double *qL, const double *qR,
+                    const double *sf, double Vf, double *Lout, double *Rout, double *lam)
+{
+    if (ndim != 2 && ndim != 3)
+        return -1;
+    charsys S;
+    int nv = ndim + 2;
+    roe_system(ndim, gamma, qL, qR, sf, Vf, &S);
+    for (int a = 0; a < nv; a++) {
+        for (int b = 0; b < nv; b++) {
+            Lout[a * nv + b] = S.L[a][b];
+            Rout[a * nv + b] = S.R[a][b];
+        }
+        lam[a] = S.lam[a];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* reconstructions                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* WENO5-JS, eq. (weno) with eq. (weno_wights); v = (f_{i-2} .. f_{i+2}).
+ * Readings: q0 = f_{i-2}/3 - 7 f_{i-1}/6 + 11 f_i/6 (the printed 7/6 on f_i
+ * breaks consistency), and the weight denominator sums C_r/(beta_r+eps)^2. */
+double fpo_weno5(const double v[5], double eps)
+{
+    const double C[3] = {1.0 / 10.0, 3.0 / 5.0, 3.0 / 10.0};
+    double q[3], beta[3], alpha[3], asum = 0.0, out = 0.0;
+    q[0] = v[0] / 3.0 - 7.0 * v[1] / 6.0 + 11.0 * v[2] / 6.0;
+    q[1] = -v[1] / 6.0 + 5.0 * v[2] / 6.0 + v[3] / 3.0;
+    q[2] = v[2] / 3.0 + 5.0 * v[3] / 6.0 - v[4] / 6.0;
+    beta[0] = 0.25 * pow(v[0] - 4.0 * v[1] + 3.0 * v[2], 2)
+              + 13.0 / 12.0 * pow(v[0] - 2.0 * v[1] + v[2], 2);
+    beta[1] = 0.25 * pow(-v[1] + v[3], 2) + 13.0 / 12.0 * pow(v[1] - 2.0 * v[2] + v[3], 2);
+    beta[2] = 0.25 * pow(-3.0 * v[2] + 4.0 * v[3] - v[4], 2)
+              + 13.0 / 12.0 * pow(v[2] - 2.0 * v[3] + v[4], 2);
+    for (int k = 0; k < 3; k++) {
+        alpha[k] = C[k] / pow(beta[k] + eps, 2);
+        asum += alpha[k];
+    }
+    for (int k = 0; k < 3; k++)
+        out += alpha[k] / asum * q[k];
+    return out;
+}
+
+/* fifth-order linear upwind, eq. (linear_upwind), "+" orientation */
+double fpo_linear_upwind5(const double v[5])
+{
+    return (2.0 * v[0] - 13.0 * v[1] + 47.0 * v[2] + 27.0 * v[3] - 3.0 * v[4]) / 60.0;
+}
+
+static double reconstruct(const fpo_scheme *sc, const double v[5])
+{
+    return sc->recon == 1 ? fpo_linear_upwind5(v) : fpo_weno5(v, sc->eps);
+}
+
+/* ------------------------------------------------------------------------ */
+/* face flux with the reformulated dissipation (Sec. 3)                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int ndim, nv;
+    const double *Q[NVMAX]; /* Q[v][m], m relative to the first interior node */
+    const double *V;        /* 1/J */
+    const double *S[3];     /* metric vector of the sweep direction, s_{d,c} */
+} line_t;
+
+/* F'_{i+1/2} for the face between nodes i and i+1 of a line */
+static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, double *Fp)
+{
+    const int ndim = ln->ndim, nv = ln->nv, Y = sc->Y, h = Y / 2;
+    const double gam = sc->gamma;
+    double w[8];
+
+    /* (1) cell-face reference state: (1/J)_{i+1/2}, Q~_{i+1/2} and the face
+     * metrics by the central interpolation of the metric order Y
+     * (eqs. QdJ_star, 1dJ, xidJ; Remark 3 asks for the metric scheme), and
+     * Q* = Q~_{i+1/2} / (1/J)_{i+1/2} (eq. Q_star). */
+    double Vf, Qtf[NVMAX], sf[3] = {0, 0, 0}, Qs[NVMAX];
+    for (int m = 0; m < Y; m++)
+        w[m] = ln->V[i - h + 1 + m];
+    Vf = fpo_face_interp(Y, w);
+    for (int v = 0; v < nv; v++) {
+        for (int m = 0; m < Y; m++)
+            w[m] = ln->Q[v][i - h + 1 + m] * ln->V[i - h + 1 + m];
+        Qtf[v] = fpo_face_interp(Y, w);
+    }
+    for (int c = 0; c < ndim; c++) {
+        for (int m = 0; m < Y; m++)
+            w[m] = ln->S[c][i - h + 1 + m];
+        sf[c] = fpo_face_interp(Y, w);
+    }
+    for (int v = 0; v < nv; v++)
+        Qs[v] = sc->reformulated ? Qtf[v] / Vf : 0.0;
+
+    /* (2) fluxes F*, G*, H* of Q* and the face flux
+     * F~*_{i+1/2} = F* (xi_x/J)_{i+1/2} + G* (xi_y/J)_{i+1/2} + H* (xi_z/J)_{i+1/2} */
+    double Fs[3][NVMAX], Fts[NVMAX];
+    memset(Fs, 0, sizeof Fs);
+    if (sc->reformulated)
+        phys_flux(ndim, gam, Qs, Fs);
+    for (int v = 0; v < nv; v++) {
+        Fts[v] = 0.0;
+        for (int c = 0; c < ndim; c++)
+            Fts[v] += Fs[c][v] * sf[c];
+    }
+
+    /* (3) reference-subtracted stencil values, m = i-2 .. i+3:
+     * dQ~_m = (Q_m - Q*)/J_m and
+     * dF~_m = (F_m - F*) (xi_x/J)_m + (G_m - G*) (xi_y/J)_m + (H_m - H*) (xi_z/J)_m
+     * (eqs. Linear_upwind_LFspliting and flux_split_detail) */
+    double dQt[6][NVMAX], dFt[6][NVMAX];
+    for (int r = 0; r < 6; r++) {
+        int m = i - 2 + r;
+        double Qm[NVMAX], Fm[3][NVMAX];
+        for (int v = 0; v < nv; v++)
+            Qm[v] = ln->Q[v][m];
+        phys_flux(ndim, gam, Qm, Fm);
+        for (int v = 0; v < nv; v++) {
+            dQt[r][v] = (Qm[v] - Qs[v]) * ln->V[m];
+            dFt[r][v] = 0.0;
+            for (int c = 0; c < ndim; c++)
+                dFt[r][v] += (Fm[c][v] - Fs[c][v]) * ln->S[c][m];
+        }
+    }
+
+    /* (4) Roe-averaged characteristic system at i+1/2 */
+    double QL[NVMAX], QR[NVMAX];
+    for (int v = 0; v < nv; v++) {
+        QL[v] = ln->Q[v][i];
+        QR[v] = ln->Q[v][i + 1];
+    }
+    charsys S;
+    roe_system(ndim, gam, QL, QR, sf, Vf, &S);
+
+    /* (5) local Lax-Friedrichs speed of every field: the largest
+     * sigma |n . u_m + kappa_s c_m| over the stencil m = i-2 .. i+3 */
+    double lam[NVMAX];
+    for (int s = 0; s < nv; s++) {
+        double kap = s == 0 ? -1.0 : (s == nv - 1 ? 1.0 : 0.0);
+        lam[s] = 0.0;
+        for (int r = 0; r < 6; r++) {
+            int m = i - 2 + r;
+            double Qm[NVMAX];
+            for (int v = 0; v < nv; v++)
+                Qm[v] = ln->Q[v][m];
+            double unm = 0.0;
+            for (int c = 0; c < ndim; c++)
+                unm += S.n[c] * Qm[1 + c] / Qm[0];
+            double cm = sqrt(gam * pressure(ndim, gam, Qm) / Qm[0]);
+            double a = S.sigma * fabs(unm + kap * cm);
+            if (a > lam[s])
+                lam[s] = a;
+        }
+    }
+
+    /* (6) characteristic projection and Lax-Friedrichs splitting:
+     * F~^{s,+-}_m = 1/2 l_s . (dF~_m +- lambda_s dQ~_m) */
+    double vp[NVMAX][6], vm[NVMAX][6];
+    for (int s = 0; s < nv; s++)
+        for (int r = 0; r < 6; r++) {
+            double a = 0.0, b = 0.0;
+            for (int v = 0; v < nv; v++) {
+                a += S.L[s][v] * dFt[r][v];
+                b += S.L[s][v] * dQt[r][v];
+            }
+            vp[s][r] = 0.5 * (a + lam[s] * b);
+            vm[s][r] = 0.5 * (a - lam[s] * b);
+        }
+
+    /* (7) reconstruction of both split parts at the face: the "+" part from
+     * m = i-2 .. i+2, the "-" part mirrored from m = i+3 .. i-1 */
+    double hp[NVMAX], hm[NVMAX];
+    for (int s = 0; s < nv; s++) {
+        double a[5] = {vp[s][0], vp[s][1], vp[s][2], vp[s][3], vp[s][4]};
+        double b[5] = {vm[s][5], vm[s][4], vm[s][3], vm[s][2], vm[s][1]};
+        hp[s] = reconstruct(sc, a);
+        hm[s] = reconstruct(sc, b);
+    }
+
+    /* (8) back to physical space and add the reference flux back
+     * (eq. my_point1): F'_{i+1/2} = F~*_{i+1/2} + sum_s r_s (h+_s + h-_s) */
+    for (int v = 0; v < nv; v++) {
+        double sum = 0.0;
+        for (int s = 0; s < nv; s++)
+            sum += S.R[v][s] * (hp[s] + hm[s]);
+        Fp[v] = Fts[v] + sum;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* ghost layers, lines, residual                                            */
+/* ------------------------------------------------------------------------ */
+
+/* copy of q with periodic ghost layers taken from the periodic image */
+static double *filled_copy(const layout *L, const double *q)
+{
+    double *w = (double *)malloc(sizeof(double) * L->nv * L->vol);
+    if (!w)
+        return NULL;
+    memcpy(w, q, sizeof(double) * L->nv * L->vol);
+    for (int d = 0; d < L->ndim; d++) {
+        if (L->bc[d] != 0)
+            continue;
+        for (int k = (L->ndim == 3 ? -L->g : 0); k < (L->ndim == 3 ? L->n[2] + L->g : 1); k++)
+            for (int j = -L->g; j < L->n[1] + L->g; j++)
+                for (int i = -L->g; i < L->n[0] + L->g; i++) {
+                    int p[3] = {i, j, k};
+                    if (p[d] >= 0 && p[d] < L->n[d])
+                        continue;
+                    int s[3] = {i, j, k};
+                    s[d] = ((p[d] % L->n[d]) + L->n[d]) % L->n[d];
+                    for (int v = 0; v < L->nv; v++)
+                        w[v * L->vol + at(L, i, j, k)] = w[v * L->vol + at(L, s[0], s[1], s[2])];
+                }
+    }
+    return w;
+}
+
+/* gather the line through (p with p[d] free) into buf; fills ln */
+static void gather_line(const layout *L, const double *q, const double *met, int d,
+                        const int p[3], double *buf, line_t *ln)
+{
+    int len = L->n[d] + 2 * L->g;
+    int nsd = L->ndim; /* metric components per direction */
+    ln->ndim = L->ndim;
+    ln->nv = L->nv;
+    for (int t = 0; t < len; t++) {
+        int c3[3] = {p[0], p[1], p[2]};
+        c3[d] = t - L->g;
+        long off = at(L, c3[0], c3[1], c3[2]);
+        for (int v = 0; v < L->nv; v++)
+            buf[v * len + t] = q[v * L->vol + off];
+        buf[L->nv * len + t] = met[(L->nmet - 1) * L->vol + off];
+        for (int c = 0; c < nsd; c++)
+            buf[(L->nv + 1 + c) * len + t] = met[(d * nsd + c) * L->vol + off];
+    }
+    for (int v = 0; v < L->nv; v++)
+        ln->Q[v] = buf + v * len + L->g;
+    ln->V = buf + L->nv * len + L->g;
+    for (int c = 0; c < nsd; c++)
+        ln->S[c] = buf + (L->nv + 1 + c) * len + L->g;
+}
+
+static int check_scheme(const layout *L, const fpo_scheme *sc)
+{
+    if (!sc || (sc->recon != 0 && sc->recon != 1) || (sc->reformulated != 0 && sc->reformulated != 1))
+        return -1;
+    if (sc->Y != 2 && sc->Y != 4 && sc->Y != 6 && sc->Y != 8)
+        return -1;
+    /* the stencil reaches 3 nodes; the face interpolation Y/2 nodes */
+    if (L->g < 3 || L->g < sc->Y / 2)
+        return -1;
+    if (!(sc->gamma > 1.0) || !(sc->eps > 0.0))
+        return -1;
+    return 0;
+}
+
+/* the two axes other than d */
+static void other_axes(int d, int *a, int *b)
+{
+    *a = d == 0 ? 1 : 0;
+    *b = d == 2 ? 1 : 2;
+}
+
+int fpo_face_fluxes(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                    const double *q, int dir, double *flux)
+{
+    layout L;
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || dir < 0 || dir >= L.ndim)
+        return -1;
+    double *qf = filled_copy(&L, q);
+    if (!qf)
+        return -1;
+    int a, b;
+    other_axes(dir, &a, &b);
+    int nf = L.n[dir] + 1;
+    int ext[3] = {L.n[0], L.n[1], L.n[2]};
+    ext[dir] = nf;
+    long fvol = (long)ext[0] * ext[1] * ext[2];
+    int na = L.n[a], nb = L.n[b];
+    int len = L.n[dir] + 2 * L.g;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * len * (L.nv + 1 + L.ndim));
+        line_t ln;
+#pragma omp for collapse(2) schedule(static)
+        for (int ib = 0; ib < nb; ib++)
+            for (int ia = 0; ia < na; ia++) {
+                int p[3] = {0, 0, 0};
+                p[a] = ia;
+                p[b] = ib;
+                gather_line(&L, qf, met, dir, p, buf, &ln);
+                for (int f = 0; f < nf; f++) {
+                    double F[NVMAX];
+                    face_flux(sc, &ln, f - 1, F);
+                    int c3[3] = {p[0], p[1], p[2]};
+                    c3[dir] = f;
+                    long off = ((long)c3[2] * ext[1] + c3[1]) * ext[0] + c3[0];
+                    for (int v = 0; v < L.nv; v++)
+                        flux[v * fvol + off] = F[v];
+                }
+            }
+        free(buf);
+    }
+    free(qf);
+    return 0;
+}
+
+/* residual of eq. (aderivative) summed over the directions in the order
+ * xi, eta, zeta: dQ/dt = -(1/J)^{-1} sum_d (F'_{i+1/2} - F'_{i-1/2}) */
+static int residual_filled(const layout *L, const fpo_scheme *sc, const double *met,
+                           const double *qf, double *dqdt)
+{
+    long tot = (long)L->nv * L->vol;
+    double *acc = (double *)calloc(tot, sizeof(double));
+    if (!acc)
+        return -1;
+    for (int d = 0; d < L->ndim; d++) {
+        int a, b;
+        other_axes(d, &a, &b);
+        int len = L->n[d] + 2 * L->g;
+        int na = L->n[a], nb = L->n[b];
+#pragma omp parallel
+        {
+            double *buf = (double *)malloc(sizeof(double) * len * (L->nv + 1 + L->ndim));
+            double *F = (double *)malloc(sizeof(double) * (L->n[d] + 1) * NVMAX);
+            line_t ln;
+#pragma omp for collapse(2) schedule(static)
+            for (int ib = 0; ib < nb; ib++)
+                for (int ia = 0; ia < na; ia++) {
+                    int p[3] = {0, 0, 0};
+                    p[a] = ia;
+                    p[b] = ib;
+                    gather_line(L, qf, met, d, p, buf, &ln);
+                    for (int f = 0; f <= L->n[d]; f++)
+                        face_flux(sc, &ln, f - 1, F + (long)f * NVMAX);
+                    for (int i = 0; i < L->n[d]; i++) {
+                        int c3[3] = {p[0], p[1], p[2]};
+                        c3[d] = i;
+                        long off = at(L, c3[0], c3[1], c3[2]);
+                        for (int v = 0; v < L->nv; v++)
+                            acc[v * L->vol + off] +=
+                                F[(long)(i + 1) * NVMAX + v] - F[(long)i * NVMAX + v];
+                    }
+                }
+            free(F);
+            free(buf);
+        }
+    }
+    memset(dqdt, 0, sizeof(double) * tot);
+    for (int k = 0; k < L->n[2]; k++)
+        for (int j = 0; j < L->n[1]; j++)
+            for (int i = 0; i < L->n[0]; i++) {
+                long off = at(L, i, j, k);
+                double V = met[(L->nmet - 1) * L->vol + off];
+                for (int v = 0; v < L->nv; v++)
+                    dqdt[v * L->vol + off] = -acc[v * L->vol + off] / V;
+            }
+    free(acc);
+    return 0;
+}
+
+int fpo_residual(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                 const double *q, double *dqdt)
+{
+    layout L;
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || !met || !q || !dqdt)
+        return -1;
+    double *qf = filled_copy(&L, q);
+    if (!qf)
+        return -1;
+    int rc = residual_filled(&L, sc, met, qf, dqdt);
+    free(qf);
+    return rc;
+}
+
+int fpo_residual_at(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                    const double *q, int npts, const int *ijk, double *out)
+{
+    layout L;
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || npts < 0)
+        return -1;
+    for (int t = 0; t < npts; t++)
+        for (int d = 0; d < L.ndim; d++) {
+            int c = ijk[3 * t + d];
+            if (c < 0 || c >= L.n[d])
+                return -1;
+        }
+    int maxlen = 0;
+    for (int d = 0; d < L.ndim; d++)
+        if (L.n[d] + 2 * L.g > maxlen)
+            maxlen = L.n[d] + 2 * L.g;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * maxlen * (L.nv + 1 + L.ndim));
+        double *qline = (double *)malloc(sizeof(double) * maxlen * L.nv);
+        line_t ln;
+#pragma omp for schedule(dynamic, 8)
+        for (int t = 0; t < npts; t++) {
+            int p[3] = {ijk[3 * t], ijk[3 * t + 1], L.ndim == 3 ? ijk[3 * t + 2] : 0};
+            double acc[NVMAX] = {0, 0, 0, 0, 0};
+            for (int d = 0; d < L.ndim; d++) {
+                gather_line(&L, q, met, d, p, buf, &ln);
+                /* periodic ghost values come from the periodic image */
+                int len = L.n[d] + 2 * L.g;
+                if (L.bc[d] == 0) {
+                    for (int v = 0; v < L.nv; v++) {
+                        for (int tt = 0; tt < len; tt++) {
+                            int node = tt - L.g;
+                            int src = ((node % L.n[d]) + L.n[d]) % L.n[d];
+                            qline[v * len + tt] = ln.Q[v][src];
+                        }
+                        memcpy(buf + v * len, qline + v * len, sizeof(double) * len);
+                    }
+                }
+                double Fm[NVMAX], Fpl[NVMAX];
+                face_flux(sc, &ln, p[d] - 1, Fm);
+                face_flux(sc, &ln, p[d], Fpl);
+                for (int v = 0; v < L.nv; v++)
+                    acc[v] += Fpl[v] - Fm[v];
+            }
+            double V = met[(L.nmet - 1) * L.vol + at(&L, p[0], p[1], p[2])];
+            for (int v = 0; v < L.nv; v++)
+                out[(long)L.nv * t + v] = -acc[v] / V;
+        }
+        free(qline);
+        free(buf);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* third-order TVD Runge-Kutta (Sec. 2.2)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Q1 = Qn + dt L(Qn); Q2 = 3/4 Qn + 1/4 (Q1 + dt L(Q1));
+ * Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2)); interior nodes only */
+int fpo_rk3_step(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                 double *q, double dt)
+{
+    layout L;
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || !met || !q)
+        return -1;
+    long tot = (long)L.nv * L.vol;
+    double *q0 = (double *)malloc(sizeof(double) * tot);
+    double *qs = (double *)malloc(sizeof(double) * tot);
+    double *k = (double *)malloc(sizeof(double) * tot);
+    if (!q0 || !qs || !k) {
+        free(q0);
+        free(qs);
+        free(k);
+        return -1;
+    }
+    memcpy(q0, q, sizeof(double) * tot);
+    memcpy(qs, q, sizeof(double) * tot);
+    const double a[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+    const double b[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+    int rc = 0;
+    for (int st = 0; st < 3 && !rc; st++) {
+        double *qf = filled_copy(&L, qs);
+        if (!qf) {
+            rc = -1;
+            break;
+        }
+        rc = residual_filled(&L, sc, met, qf, k);
+        free(qf);
+        for (int v = 0; v < L.nv; v++)
+            for (int kk = 0; kk < L.n[2]; kk++)
+                for (int j = 0; j < L.n[1]; j++)
+                    for (int i = 0; i < L.n[0]; i++) {
+                        long off = v * L.vol + at(&L, i, j, kk);
+                        double upd = qs[off] + dt * k[off];
+                        qs[off] = st == 0 ? upd : a[st] * q0[off] + b[st] * upd;
+                    }
+    }
+    if (!rc)
+        memcpy(q, qs, sizeof(double) * tot);
+    free(q0);
+    free(qs);
+    free(k);
+    return rc;
+}
+
+int fpo_solve(const fpo_grid *gr, const fpo_scheme *sc, const double *met, double *q,
+              double dt, long nsteps)
+{
+    for (long s = 0; s < nsteps; s++) {
+        int rc = fpo_rk3_step(gr, sc, met, q, dt);
+        if (rc)
+            return rc;
+    }
+    return 0;
+}
+
+double fpo_max_dt(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                  const double *q, double cfl)
+{
+    layout L;
+    if (make_layout(gr, &L) || !sc)
+        return -1.0;
+    double mx = 0.0;
+    for (int k = 0; k < L.n[2]; k++)
+        for (int j = 0; j < L.n[1]; j++)
+            for (int i = 0; i < L.n[0]; i++) {
+                long off = at(&L, i, j, k);
+                double Q[NVMAX];
+                for (int v = 0; v < L.nv; v++)
+                    Q[v] = q[v * L.vol + off];
+                double c = sqrt(sc->gamma * pressure(L.ndim, sc->gamma, Q) / Q[0]);
+                double V = met[(L.nmet - 1) * L.vol + off];
+                double sum = 0.0;
+                for (int d = 0; d < L.ndim; d++) {
+                    double su = 0.0, s2 = 0.0;
+                    for (int c2 = 0; c2 < L.ndim; c2++) {
+                        double s = met[(d * L.ndim + c2) * L.vol + off];
+                        su += s * Q[1 + c2] / Q[0];
+                        s2 += s * s;
+                    }
+                    sum += fabs(su) + c * sqrt(s2);
+                }
+                sum /= V;
+                if (sum > mx)
+                    mx = sum;
+            }
+    return cfl / mx;
+}
+
+int fpo_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void fpo_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

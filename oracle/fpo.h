@@ -1,0 +1,91 @@
+/*
+ * fpo.h -- plain FP64 CPU oracle of the free-stream-preserving conservative
+ * finite-difference scheme with reformulated upwind dissipation
+ * (Su, Cai, Pan, Hu, "Reformulated dissipation for the free-stream preserving
+ * of the conservative finite difference schemes on curvilinear grids").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against the paper.  It shares no code, header, table or helper with the GPU
+ * path; nothing in the product links or calls it.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it.
+ *
+ * Array layout (all host memory, float64, C order, i fastest):
+ *   state  q  : [nv][Nk][Nj][Ni], N_d = n_d + 2g, nv = 5 (3D) or 4 (2D);
+ *               in 2D Nk = 1.
+ *   metrics   : [nmet][Nk][Nj][Ni], nmet = 10 (3D): xi_x/J, xi_y/J, xi_z/J,
+ *               eta_x/J .. eta_z/J, zeta_x/J .. zeta_z/J, 1/J;
+ *               nmet = 5 (2D): xi_x/J, xi_y/J, eta_x/J, eta_y/J, 1/J.
+ *   coords    : [ndim][...] with extents n_d + 2(g + Y/2) (2D: two axes).
+ * Boundary kinds per axis: 0 = periodic (ghost layers of q are ignored and
+ * taken from the periodic image), 1 = frozen (ghost layers of q are read and
+ * never changed).
+ * Return values: 0 on success, -1 on invalid arguments.
+ */
+#ifndef FPO_H
+#define FPO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int ndim;   /* 2 or 3 */
+    int n[3];   /* interior nodes per axis (n[2] = 1 in 2D) */
+    int g;      /* ghost width of state and metric arrays */
+    int bc[3];  /* 0 periodic, 1 frozen */
+} fpo_grid;
+
+typedef struct {
+    int recon;         /* 0: WENO5-JS, 1: fifth-order linear upwind */
+    int Y;             /* metric order 2, 4, 6, 8 */
+    int reformulated;  /* 1: the paper's method; 0: standard scheme (Q* = 0) */
+    double gamma;      /* ratio of specific heats */
+    double eps;        /* WENO epsilon */
+} fpo_scheme;
+
+/* Sec. 2.1 eqs. (JBabc),(JB) with the central derivative of eq. (metric_discret). */
+int fpo_metrics(const fpo_grid *gr, int Y, const double *xyz, double *met);
+/* The same quantities at selected nodes: ijk[3*p] holds (i, j, k) relative to
+ * the first interior node; out[nmet*p + c]. */
+int fpo_metrics_at(const fpo_grid *gr, int Y, const double *xyz, int npts,
+                   const int *ijk, double *out);
+
+/* Face fluxes F'_{i+1/2} of direction dir (Sec. 3) at every face of every
+ * interior line: layout [nv][..][n_dir + 1][..] (face index f = i + 1 for
+ * face i+1/2, i = -1 .. n_dir - 1), other axes interior only. */
+int fpo_face_fluxes(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                    const double *q, int dir, double *flux);
+
+/* dQ/dt = -(1/V) sum_d (F'_{i+1/2} - F'_{i-1/2}) at interior nodes; ghost
+ * entries of dqdt are set to zero. */
+int fpo_residual(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                 const double *q, double *dqdt);
+/* The residual at selected interior nodes only: out[nv*p + v]. */
+int fpo_residual_at(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                    const double *q, int npts, const int *ijk, double *out);
+
+/* One step of the third-order TVD Runge-Kutta scheme, in place on the
+ * interior of q. */
+int fpo_rk3_step(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                 double *q, double dt);
+int fpo_solve(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+              double *q, double dt, long nsteps);
+
+/* CFL time step: cfl / max_i sum_d (|s_d . u| + c |s_d|) / V. */
+double fpo_max_dt(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                  const double *q, double cfl);
+
+/* Building blocks exposed for the pins. */
+double fpo_weno5(const double v[5], double eps);       /* eq. (weno) */
+double fpo_linear_upwind5(const double v[5]);          /* eq. (linear_upwind) */
+double fpo_face_interp(int Y, const double *w);        /* eq. (metric_discret) */
+int fpo_eigensystem(int ndim, double gamma, const double *qL, const double *qR,
+                    const double *sf, double Vf, double *L, double *R, double *lam);
+int fpo_num_threads(void);
+void fpo_set_num_threads(int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPO_H */

@@ -1,0 +1,269 @@
+"""Seeded synthetic inputs: curvilinear grids and initial states.
+
+This module holds no arithmetic of the numerical method.  It only produces
+node coordinates (with ghost images) and conserved states, in the array
+layout every entry point uses:
+
+* state ``q``: ``(nv, Nk, Nj, Ni)`` in 3D or ``(nv, Nj, Ni)`` in 2D, float64,
+  C order (i fastest), ``N_d = n_d + 2*g``; ``nv`` = 5 (3D) or 4 (2D),
+  variables (rho, rho*u, rho*v[, rho*w], rho*E);
+* metrics: ``(nmet, ...)`` with the state extents, ``nmet`` = 10 in 3D
+  (xi_x, xi_y, xi_z, eta_x, ..., zeta_z, all divided by J, then 1/J) and 5 in
+  2D (xi_x, xi_y, eta_x, eta_y divided by J, then 1/J);
+* coordinates: ``(ndim, ...)`` with extents ``n_d + 2*(g + Y/2)``, where Y is
+  the metric order; ghost nodes hold the periodic image (shifted by the period)
+  or the analytic mapping evaluated out of range.  ``g + Y/2`` ghost
+  coordinates are what the symmetric conservative metrics need at the
+  outermost state ghost node.
+
+The grid recipes follow the test problems of Sec. 4.1 of the paper (wavy and
+randomly perturbed grids, uniform flow, isentropic vortex) and the synthetic
+workloads derived from them.  Random numbers come from numpy's PCG64 with an
+explicit seed.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def coord_ghost(g: int, Y: int) -> int:
+    """Ghost width of coordinate arrays: state ghost width plus half the
+    metric order (the reach of one central derivative of order Y)."""
+    return g + Y // 2
+
+
+def state_shape(ndim: int, n, g: int, nv: int | None = None):
+    n = _n3(ndim, n)
+    if nv is None:
+        nv = ndim + 2
+    if ndim == 2:
+        return (nv, n[1] + 2 * g, n[0] + 2 * g)
+    return (nv, n[2] + 2 * g, n[1] + 2 * g, n[0] + 2 * g)
+
+
+def metric_shape(ndim: int, n, g: int):
+    return state_shape(ndim, n, g, nv=10 if ndim == 3 else 5)
+
+
+def coord_shape(ndim: int, n, g: int, Y: int):
+    n = _n3(ndim, n)
+    gc = coord_ghost(g, Y)
+    if ndim == 2:
+        return (2, n[1] + 2 * gc, n[0] + 2 * gc)
+    return (3, n[2] + 2 * gc, n[1] + 2 * gc, n[0] + 2 * gc)
+
+
+def _n3(ndim, n):
+    if np.isscalar(n):
+        n = [int(n)] * ndim
+    n = [int(v) for v in n]
+    if ndim == 2:
+        return [n[0], n[1], 1]
+    return n
+
+
+def _jitter_field(ndim, n, frac, spacing, rng):
+    """Displacement of fixed magnitude ``frac*spacing`` in a uniformly random
+    direction, one per unique node; shape (ndim, [nk,] nj, ni)."""
+    shape = tuple(reversed(n[:ndim]))
+    if frac == 0.0:
+        return np.zeros((ndim,) + shape)
+    if ndim == 2:
+        th = rng.uniform(0.0, 2.0 * math.pi, size=shape)
+        d = np.stack([np.cos(th), np.sin(th)])
+    else:
+        v = rng.standard_normal(size=(3,) + shape)
+        d = v / np.linalg.norm(v, axis=0, keepdims=True)
+    return d * (frac * spacing)
+
+
+def _periodic_take(field, ndim, n, gc):
+    """Evaluate a per-unique-node field at indices -gc..n+gc-1 by periodicity."""
+    idx = [np.arange(-gc, n[d] + gc) % n[d] for d in range(ndim)]
+    if ndim == 2:
+        return field[:, idx[1][:, None], idx[0][None, :]]
+    return field[:, idx[2][:, None, None], idx[1][None, :, None], idx[0][None, None, :]]
+
+
+def wavy_grid(ndim: int, n, L: float, g: int, Y: int, amp: float = 0.1,
+              jitter: float = 0.0, seed: int = 0) -> np.ndarray:
+    """Periodic wavy grid on [-L/2, L/2)^dim with node spacing L/n.
+
+    2D: ``x = xi + A*s(xi)*s(eta)``, ``y = eta + A*s(xi)*s(eta)``;
+    3D: ``x = xi + P``, ``y = eta + P``, ``z = zeta + P`` with
+    ``P = A*s(xi)*s(eta)*s(zeta)``, ``s(t) = sin(2*pi*(t + L/2)/L)`` and
+    ``A = amp*L``.  Optional jitter: ``jitter*L/n`` in a random direction per
+    unique node, carried to ghost images (periodic).  Ghost nodes are the
+    mapping evaluated out of range plus the image's jitter, so
+    ``x(i + n) = x(i) + L``.
+    """
+    n3 = _n3(ndim, n)
+    gc = coord_ghost(g, Y)
+    h = L / n3[0]
+    if any(abs(L / n3[d] - h) > 1e-15 * L for d in range(ndim)):
+        raise ValueError("wavy_grid needs the same node count on every axis")
+    ax = [-L / 2 + np.arange(-gc, n3[d] + gc) * (L / n3[d]) for d in range(ndim)]
+    s = [np.sin(2.0 * math.pi * (a + L / 2) / L) for a in ax]
+    A = amp * L
+    if ndim == 2:
+        eta, xi = np.meshgrid(ax[1], ax[0], indexing="ij")
+        P = A * s[1][:, None] * s[0][None, :]
+        xyz = np.stack([xi + P, eta + P])
+    else:
+        zeta, eta, xi = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        P = A * s[2][:, None, None] * s[1][None, :, None] * s[0][None, None, :]
+        xyz = np.stack([xi + P, eta + P, zeta + P])
+    if jitter:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        jf = _jitter_field(ndim, n3, jitter, h, rng)
+        xyz = xyz + _periodic_take(jf, ndim, n3, gc)
+    return np.ascontiguousarray(xyz)
+
+
+def paper_wavy_grid_2d(n: int, g: int, Y: int, L: float = 20.0, A: float = 0.6,
+                       waves: int = 4) -> np.ndarray:
+    """The 2D wavy grid of the free-stream test (Sec. 4.1.1): the x
+    coordinate is displaced by ``A*sin(2*pi*waves*(eta - ymin)/L)`` and the y
+    coordinate by ``A*sin(2*pi*waves*(xi - xmin)/L)``; ``n`` unique nodes per
+    axis (the paper's 21 points include the periodic duplicate, so n = 20)."""
+    gc = coord_ghost(g, Y)
+    a = -L / 2 + np.arange(-gc, n + gc) * (L / n)
+    eta, xi = np.meshgrid(a, a, indexing="ij")
+    x = xi + A * np.sin(2.0 * math.pi * waves * (eta + L / 2) / L)
+    y = eta + A * np.sin(2.0 * math.pi * waves * (xi + L / 2) / L)
+    return np.ascontiguousarray(np.stack([x, y]))
+
+
+def random_grid_2d(n: int, g: int, Y: int, L: float = 20.0, frac: float = 0.2,
+                   seed: int = 0) -> np.ndarray:
+    """Cartesian grid with every unique node moved by ``frac`` of the spacing
+    in a random direction (the random grid of Sec. 4.1.1)."""
+    return wavy_grid(2, n, L, g, Y, amp=0.0, jitter=frac, seed=seed)
+
+
+def cartesian_grid(ndim: int, n, g: int, Y: int, spacing=1.0, origin=0.0) -> np.ndarray:
+    """Uniform Cartesian grid (possibly anisotropic spacing per axis)."""
+    n3 = _n3(ndim, n)
+    gc = coord_ghost(g, Y)
+    sp = [spacing] * ndim if np.isscalar(spacing) else list(spacing)
+    ax = [origin + np.arange(-gc, n3[d] + gc) * sp[d] for d in range(ndim)]
+    if ndim == 2:
+        eta, xi = np.meshgrid(ax[1], ax[0], indexing="ij")
+        return np.ascontiguousarray(np.stack([xi, eta]))
+    zeta, eta, xi = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.ascontiguousarray(np.stack([xi, eta, zeta]))
+
+
+def affine_grid(ndim: int, n, g: int, Y: int, A: np.ndarray, b=None) -> np.ndarray:
+    """x = A @ (i, j[, k]) + b evaluated at every coordinate node."""
+    n3 = _n3(ndim, n)
+    gc = coord_ghost(g, Y)
+    ax = [np.arange(-gc, n3[d] + gc, dtype=np.float64) for d in range(ndim)]
+    A = np.asarray(A, dtype=np.float64)
+    b = np.zeros(ndim) if b is None else np.asarray(b, dtype=np.float64)
+    if ndim == 2:
+        J, I = np.meshgrid(ax[1], ax[0], indexing="ij")
+        comp = [I, J]
+    else:
+        K, J, I = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        comp = [I, J, K]
+    out = np.stack([sum(A[c, e] * comp[e] for e in range(ndim)) + b[c] for c in range(ndim)])
+    return np.ascontiguousarray(out)
+
+
+def state_nodes(xyz: np.ndarray, g: int, Y: int) -> np.ndarray:
+    """Coordinates of the state nodes (interior plus g ghosts) cut out of a
+    coordinate array."""
+    ndim = xyz.shape[0]
+    h = Y // 2
+    sl = (slice(None),) + (slice(h, -h),) * ndim
+    return np.ascontiguousarray(xyz[sl])
+
+
+# ----------------------------------------------------------------------------
+# states
+# ----------------------------------------------------------------------------
+
+def primitive_to_conserved(rho, vel, p, gamma=GAMMA):
+    """(rho, velocity components, p) -> conserved (rho, rho*u_k, rho*E)."""
+    ke = 0.5 * sum(v * v for v in vel)
+    E = p / ((gamma - 1.0) * rho) + ke
+    return np.stack([rho] + [rho * v for v in vel] + [rho * E])
+
+
+def uniform_state(ndim: int, n, g: int, rho: float, vel, p: float, gamma=GAMMA) -> np.ndarray:
+    shape = state_shape(ndim, n, g)[1:]
+    vel = list(vel)[:ndim]
+    out = primitive_to_conserved(np.full(shape, rho), [np.full(shape, v) for v in vel],
+                                 np.full(shape, p), gamma)
+    return np.ascontiguousarray(out)
+
+
+def mach_velocity(mach: float, direction, rho=GAMMA, p=1.0, gamma=GAMMA):
+    c = math.sqrt(gamma * p / rho)
+    d = np.asarray(direction, dtype=np.float64)
+    return mach * c * d / np.linalg.norm(d)
+
+
+def direction_3d(theta_deg=20.0, phi_deg=10.0):
+    t, f = math.radians(theta_deg), math.radians(phi_deg)
+    return np.array([math.cos(t) * math.cos(f), math.sin(t) * math.cos(f), math.sin(f)])
+
+
+@dataclass
+class Vortex:
+    """Isentropic vortex of Sec. 4.1.2: velocity perturbation
+    ``eps*tau*exp(alpha*(1-tau^2))*(sin th, -cos th)`` and temperature drop
+    ``-(gamma-1)*eps^2/(4*alpha*gamma)*exp(2*alpha*(1-tau^2))`` with
+    ``tau = r/rc``, zero entropy change, on a uniform background
+    (rho_inf, vel_inf, p_inf).  In 3D the vortex is a column along z."""
+    eps: float = 5.0 / (2.0 * math.pi)
+    alpha: float = 0.5
+    rc: float = 1.0
+    center: tuple = (0.0, 0.0)
+    rho_inf: float = GAMMA
+    p_inf: float = 1.0
+    vel_inf: tuple = (0.5, 0.0, 0.0)
+    gamma: float = GAMMA
+
+    def primitives(self, x, y, t=0.0, period=None):
+        """(rho, u, v, p) at points (x, y) and time t (centre translated by
+        the background velocity; nearest periodic image if ``period``)."""
+        g = self.gamma
+        cx = self.center[0] + self.vel_inf[0] * t
+        cy = self.center[1] + self.vel_inf[1] * t
+        dx = x - cx
+        dy = y - cy
+        if period is not None:
+            dx = dx - period * np.round(dx / period)
+            dy = dy - period * np.round(dy / period)
+        r = np.sqrt(dx * dx + dy * dy)
+        tau = r / self.rc
+        ex = np.exp(self.alpha * (1.0 - tau * tau))
+        # tau*(sin th, -cos th) = (dy, -dx)/rc
+        du = self.eps * ex * dy / self.rc
+        dv = -self.eps * ex * dx / self.rc
+        dT = -(g - 1.0) * self.eps ** 2 / (4.0 * self.alpha * g) * ex * ex
+        Tinf = self.p_inf / self.rho_inf
+        T = Tinf + dT
+        rho = self.rho_inf * (T / Tinf) ** (1.0 / (g - 1.0))
+        p = rho * T
+        return rho, self.vel_inf[0] + du, self.vel_inf[1] + dv, p
+
+    def state(self, nodes: np.ndarray, t=0.0, period=None) -> np.ndarray:
+        """Conserved state at node coordinates ``nodes`` (ndim, ...)."""
+        ndim = nodes.shape[0]
+        rho, u, v, p = self.primitives(nodes[0], nodes[1], t, period)
+        vel = [u, v] if ndim == 2 else [u, v, np.full_like(u, self.vel_inf[2])]
+        return np.ascontiguousarray(primitive_to_conserved(rho, vel, p, self.gamma))
+
+
+def interior(a: np.ndarray, g: int) -> np.ndarray:
+    """View of the interior nodes of a state-like array (leading variable axis)."""
+    nd = a.ndim - 1
+    return a[(slice(None),) + (slice(g, -g),) * nd]
