@@ -1,0 +1,172 @@
+/*
+ * fp.h -- C ABI of the MI355X (gfx950) library for the free-stream-preserving
+ * conservative finite-difference scheme with reformulated upwind dissipation
+ * on curvilinear grids (H. Su, J. Cai, S. Pan, X. Hu, "Reformulated
+ * dissipation for the free-stream preserving of the conservative finite
+ * difference schemes on curvilinear grids", arXiv 2101.05886).
+ *
+ * Problem statement (Sec. 2 and Sec. 3 of the paper): given a stationary
+ * structured curvilinear grid and a conserved state Q of the Euler equations
+ * (eqs. NS, Q, F, G, H, EOS without the viscous terms), form the metrics and
+ * 1/J by the symmetric conservative metric method of order Y (eqs. JBabc, JB
+ * with the central schemes of eq. metric_discret), evaluate the convective
+ * residual dQ/dt = -(1/J)^{-1} sum_d (F'_{i+1/2} - F'_{i-1/2}) whose face flux
+ * F' is reconstructed by WENO5-JS (eqs. weno, weno_wights) or the fifth-order
+ * linear upwind scheme (eq. linear_upwind, eq. new_form_linear_upwind) from
+ * reference-subtracted, characteristic, Lax-Friedrichs-split stencil values
+ * with the reference flux added back (eqs. Q_star, QdJ_star, 1dJ,
+ * flux_split_detail, my_point1, xidJ), and advance it with the third-order
+ * TVD Runge-Kutta scheme (Sec. 2.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory: every array argument is DEVICE memory of the current HIP device,
+ *   float64, allocated and owned by the caller.  The library keeps no pointer
+ *   after the work it enqueued has completed, except the step graphs cached
+ *   by fp_solve (released by fp_release_cache).  Hot entry points
+ *   (fp_residual, fp_rk3_step, fp_solve, fp_face_fluxes) allocate nothing.
+ * Layout: structure of arrays, variable-major, i fastest.
+ *   state q      : [nv][Nk][Nj][Ni], N_d = n_d + 2*ghost, nv = 5 (3D) or 4
+ *                  (2D: Nk = 1) with variables (rho, rho u, rho v[, rho w], rho E);
+ *   metrics met  : [nmet][Nk][Nj][Ni]; nmet = 10 in 3D (xi_x/J, xi_y/J, xi_z/J,
+ *                  eta_x/J, eta_y/J, eta_z/J, zeta_x/J, zeta_y/J, zeta_z/J, 1/J),
+ *                  5 in 2D (xi_x/J, xi_y/J, eta_x/J, eta_y/J, 1/J);
+ *   coordinates  : [ndim][...] with extents n_d + 2*(ghost + Y/2).
+ * Boundaries, per axis: FP_BC_PERIODIC -- the ghost layers of q are ignored
+ *   (stencils wrap to the periodic image); the coordinate ghosts must hold the
+ *   periodic images shifted by the period.  FP_BC_FROZEN -- the ghost layers
+ *   of q hold caller values that are read and never written (every RK stage
+ *   reads them from q); coordinate ghosts hold the mapping evaluated out of
+ *   range.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = legacy default
+ *   stream).  Calls only enqueue work; the caller synchronises.
+ * Errors: arguments are validated before anything is enqueued; an invalid
+ *   call returns FP_EINVAL or FP_EUNSUPPORTED and enqueues nothing.  A launch
+ *   failure returns FP_EHIP.  fp_last_error() gives a thread-local message
+ *   for the last non-OK return.  No C++ exception crosses this interface.
+ * Threads: entry points are reentrant; the graph cache is mutex-guarded.
+ */
+#ifndef FP_H
+#define FP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FP_OK = 0,
+    FP_EINVAL = -1,        /* malformed arguments */
+    FP_EUNSUPPORTED = -2,  /* well-formed but not provided (e.g. metric order 3) */
+    FP_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+    FP_ENOMEM = -4,        /* a setup entry point could not allocate */
+    FP_ENONPHYS = -5       /* reserved for state checks reported to the host */
+} fp_status;
+
+enum { FP_WENO5JS = 0, FP_LINUP5 = 1 };          /* reconstruction */
+enum { FP_FP64 = 0, FP_MIXED32 = 1 };            /* precision of the characteristic part */
+enum { FP_BC_PERIODIC = 0, FP_BC_FROZEN = 1 };   /* per axis */
+
+/* One structured block.  ndim = 2 or 3; n[d] >= 1 interior nodes per axis
+ * (n[2] = 1 when ndim = 2); ghost >= 3 and ghost >= metric_order/2;
+ * a periodic axis needs n[d] >= ghost. */
+typedef struct {
+    int32_t ndim;
+    int32_t n[3];
+    int32_t ghost;
+    int32_t bc[3];
+} fp_grid;
+
+/* The discretisation.  metric_order Y in {2,4,6,8} is used for the metrics
+ * AND for the cell-face interpolation of 1/J, Q~ and the metrics inside the
+ * flux (Remark 3).  reformulated = 1 is the paper's method; 0 is the
+ * standard characteristic scheme (reference state zero), kept as the
+ * negative control of the free-stream test.  precision = FP_MIXED32 runs the
+ * characteristic projection, splitting, smoothness indicators, weights and
+ * back-projection in FP32 on the reference-subtracted differences; metrics,
+ * the reference state, subtraction, add-back and all stored state stay FP64. */
+typedef struct {
+    int32_t recon;
+    int32_t metric_order;
+    int32_t reformulated;
+    int32_t precision;
+    double gamma;     /* ratio of specific heats, > 1 (the paper: 1.4) */
+    double weno_eps;  /* WENO epsilon, > 0 (the paper: 1e-6) */
+} fp_scheme;
+
+/* Sizes in bytes of the caller-allocated arrays. */
+size_t fp_state_bytes(const fp_grid *grid);
+size_t fp_metric_bytes(const fp_grid *grid);
+size_t fp_coord_bytes(const fp_grid *grid, int32_t metric_order);
+/* Workspace of fp_rk3_step / fp_solve: three state-sized arrays (two RK
+ * stage registers and the residual accumulator). */
+size_t fp_work_bytes(const fp_grid *grid);
+
+/* Symmetric conservative metrics and 1/J of order Y (Sec. 2.1, eqs. JBabc and
+ * JB; derivatives by eq. metric_discret).  2D: xi_x/J = y_eta, xi_y/J = -x_eta,
+ * eta_x/J = -y_xi, eta_y/J = x_xi and 1/J = 1/2[(x y_eta - y x_eta)_xi +
+ * (y x_xi - x y_xi)_eta], the reduction of the 3D formulas for z = zeta.
+ * Periodic axes: computed on the interior and copied into the ghost layers;
+ * frozen axes: computed on the ghost nodes too.  Setup call (not hot). */
+fp_status fp_metrics(const fp_grid *grid, int32_t metric_order, const double *xyz,
+                     double *met, void *stream);
+
+/* Face fluxes F'_{i+1/2} of one direction (Sec. 3, eq. my_point1 with the
+ * reformulated dissipation of eqs. Linear_upwind_LFspliting and
+ * flux_split_detail) at every face of every interior line.
+ * flux: [nv][..] with extent n_dir + 1 along `dir` (index f <-> face
+ * f - 1/2), interior extents on the other axes. */
+fp_status fp_face_fluxes(const fp_grid *grid, const fp_scheme *scheme, const double *met,
+                         const double *q, int32_t dir, double *flux, void *stream);
+
+/* dQ/dt = -(1/J)^{-1} sum_{d = xi, eta, zeta} (F'_{i+1/2} - F'_{i-1/2})
+ * (eq. aderivative, directions summed in that order) at the interior nodes.
+ * Ghost entries of dqdt are not written.  q is not modified. */
+fp_status fp_residual(const fp_grid *grid, const fp_scheme *scheme, const double *met,
+                      const double *q, double *dqdt, void *stream);
+
+/* One direction of the dimension-by-dimension residual (eq. aderivative for
+ * direction `dir`): acc = -(F'_{i+1/2} - F'_{i-1/2}) when accumulate = 0, or
+ * acc -= (F'_{i+1/2} - F'_{i-1/2}) when accumulate = 1, at the interior nodes
+ * (no division by 1/J).  acc has the state layout; ghost entries are not
+ * written.  Launches exactly one kernel.  Summing the three directions in
+ * the order xi, eta, zeta and dividing by 1/J gives fp_residual. */
+fp_status fp_residual_dir(const fp_grid *grid, const fp_scheme *scheme, const double *met,
+                          const double *q, int32_t dir, double *acc, int32_t accumulate,
+                          void *stream);
+
+/* One step of the third-order TVD Runge-Kutta scheme (Sec. 2.2):
+ * Q1 = Qn + dt L(Qn); Q2 = 3/4 Qn + 1/4 (Q1 + dt L(Q1));
+ * Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2)).  In place on the interior of q;
+ * work: fp_work_bytes(grid) bytes of device memory. */
+fp_status fp_rk3_step(const fp_grid *grid, const fp_scheme *scheme, const double *met,
+                      double *q, double *work, double dt, void *stream);
+
+/* nsteps RK3 steps of fixed dt.  The first call for a given (grid, scheme,
+ * pointers, dt) captures one step into a HIP graph that later calls replay. */
+fp_status fp_solve(const fp_grid *grid, const fp_scheme *scheme, const double *met,
+                   double *q, double *work, double dt, int64_t nsteps, void *stream);
+
+/* dt = cfl / max_i sum_d (|s_d . u| + c |s_d|) (1/J)^{-1} over the interior
+ * (the convective CFL limit), written to dt_dev (device, one double). */
+fp_status fp_max_dt(const fp_grid *grid, const fp_scheme *scheme, const double *met,
+                    const double *q, double cfl, double *dt_dev, void *stream);
+
+/* flag_dev (device int32) is set to 1 if any interior node has a non-finite
+ * value, rho <= 0 or p <= 0; it is left unchanged otherwise (the caller
+ * clears it). */
+fp_status fp_check_state(const fp_grid *grid, const fp_scheme *scheme, const double *q,
+                         int32_t *flag_dev, void *stream);
+
+/* Frees the cached step graphs. */
+void fp_release_cache(void);
+
+const char *fp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FP_H */

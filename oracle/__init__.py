@@ -58,6 +58,7 @@ def lib():
         L.fpo_face_fluxes.argtypes = [gp, sp, dp, dp, C.c_int, dp]
         L.fpo_residual.argtypes = [gp, sp, dp, dp, dp]
         L.fpo_residual_at.argtypes = [gp, sp, dp, dp, C.c_int, ip, dp]
+        L.fpo_residual_at_xyz.argtypes = [gp, sp, dp, dp, C.c_int, ip, dp]
         L.fpo_rk3_step.argtypes = [gp, sp, dp, dp, C.c_double]
         L.fpo_solve.argtypes = [gp, sp, dp, dp, C.c_double, C.c_long]
         L.fpo_max_dt.argtypes = [gp, sp, dp, dp, C.c_double]
@@ -181,6 +182,16 @@ def residual_at(grid: Grid, scheme: Scheme, met, q, ijk) -> np.ndarray:
     out = np.zeros((ijk.shape[0], grid.nv))
     _chk(lib().fpo_residual_at(C.byref(grid.c()), C.byref(scheme.c()), _dp(met), _dp(q),
                                ijk.shape[0], _ip(ijk), _dp(out)), "residual_at")
+    return out
+
+
+def residual_at_xyz(grid: Grid, scheme: Scheme, xyz, q, ijk) -> np.ndarray:
+    """Residual at selected nodes with metrics computed from the coordinates."""
+    xyz, q = _arr(xyz), _arr(q)
+    ijk = np.ascontiguousarray(np.asarray(ijk, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((ijk.shape[0], grid.nv))
+    _chk(lib().fpo_residual_at_xyz(C.byref(grid.c()), C.byref(scheme.c()), _dp(xyz), _dp(q),
+                                   ijk.shape[0], _ip(ijk), _dp(out)), "residual_at_xyz")
     return out
 
 

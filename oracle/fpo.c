@@ -148,38 +148,48 @@ static double T(const cgrid *C, int a, int e, int b, int f, const int p[3])
     return deriv_Y(C->Y, w);
 }
 
-/* the nine metrics s_{d,c} = (d_c)/J of eq. (JBabc) at node p (3D), written
- * term by term as printed: e.g. xi_x/J = 1/2[(y_eta z)_zeta - (y_zeta z)_eta
- * + (y z_zeta)_eta - (y z_eta)_zeta] */
+/* the metrics s_{d,c} = (d_c)/J of eq. (JBabc) at node p (3D) for one
+ * direction d, written term by term as printed: e.g.
+ * xi_x/J = 1/2[(y_eta z)_zeta - (y_zeta z)_eta + (y z_zeta)_eta - (y z_eta)_zeta] */
+static void scmm3_dir(const cgrid *C, int d, const int p[3], double s[3])
+{
+    if (d == XI) {
+        /* xi_x/J */
+        s[0] = 0.5 * (T(C, CY, ETA, CZ, ZETA, p) - T(C, CY, ZETA, CZ, ETA, p)
+                      + T(C, CZ, ZETA, CY, ETA, p) - T(C, CZ, ETA, CY, ZETA, p));
+        /* xi_y/J = 1/2[(x z_eta)_zeta - (x z_zeta)_eta + (x_zeta z)_eta - (x_eta z)_zeta] */
+        s[1] = 0.5 * (T(C, CZ, ETA, CX, ZETA, p) - T(C, CZ, ZETA, CX, ETA, p)
+                      + T(C, CX, ZETA, CZ, ETA, p) - T(C, CX, ETA, CZ, ZETA, p));
+        /* xi_z/J = 1/2[(x_eta y)_zeta - (x_zeta y)_eta + (x y_zeta)_eta - (x y_eta)_zeta] */
+        s[2] = 0.5 * (T(C, CX, ETA, CY, ZETA, p) - T(C, CX, ZETA, CY, ETA, p)
+                      + T(C, CY, ZETA, CX, ETA, p) - T(C, CY, ETA, CX, ZETA, p));
+    } else if (d == ETA) {
+        /* eta_x/J = 1/2[(y_zeta z)_xi - (y_xi z)_zeta + (y z_xi)_zeta - (y z_zeta)_xi] */
+        s[0] = 0.5 * (T(C, CY, ZETA, CZ, XI, p) - T(C, CY, XI, CZ, ZETA, p)
+                      + T(C, CZ, XI, CY, ZETA, p) - T(C, CZ, ZETA, CY, XI, p));
+        /* eta_y/J = 1/2[(x z_zeta)_xi - (x z_xi)_zeta + (x_xi z)_zeta - (x_zeta z)_xi] */
+        s[1] = 0.5 * (T(C, CZ, ZETA, CX, XI, p) - T(C, CZ, XI, CX, ZETA, p)
+                      + T(C, CX, XI, CZ, ZETA, p) - T(C, CX, ZETA, CZ, XI, p));
+        /* eta_z/J = 1/2[(x_zeta y)_xi - (x_xi y)_zeta + (x y_xi)_zeta - (x y_zeta)_xi] */
+        s[2] = 0.5 * (T(C, CX, ZETA, CY, XI, p) - T(C, CX, XI, CY, ZETA, p)
+                      + T(C, CY, XI, CX, ZETA, p) - T(C, CY, ZETA, CX, XI, p));
+    } else {
+        /* zeta_x/J = 1/2[(y_xi z)_eta - (y_eta z)_xi + (y z_eta)_xi - (y z_xi)_eta] */
+        s[0] = 0.5 * (T(C, CY, XI, CZ, ETA, p) - T(C, CY, ETA, CZ, XI, p)
+                      + T(C, CZ, ETA, CY, XI, p) - T(C, CZ, XI, CY, ETA, p));
+        /* zeta_y/J = 1/2[(x z_xi)_eta - (x z_eta)_xi + (x_eta z)_xi - (x_xi z)_eta] */
+        s[1] = 0.5 * (T(C, CZ, XI, CX, ETA, p) - T(C, CZ, ETA, CX, XI, p)
+                      + T(C, CX, ETA, CZ, XI, p) - T(C, CX, XI, CZ, ETA, p));
+        /* zeta_z/J = 1/2[(x_xi y)_eta - (x_eta y)_xi + (x y_eta)_xi - (x y_xi)_eta] */
+        s[2] = 0.5 * (T(C, CX, XI, CY, ETA, p) - T(C, CX, ETA, CY, XI, p)
+                      + T(C, CY, ETA, CX, XI, p) - T(C, CY, XI, CX, ETA, p));
+    }
+}
+
 static void scmm3(const cgrid *C, const int p[3], double s[9])
 {
-    /* xi_x/J */
-    s[0] = 0.5 * (T(C, CY, ETA, CZ, ZETA, p) - T(C, CY, ZETA, CZ, ETA, p)
-                  + T(C, CZ, ZETA, CY, ETA, p) - T(C, CZ, ETA, CY, ZETA, p));
-    /* xi_y/J = 1/2[(x z_eta)_zeta - (x z_zeta)_eta + (x_zeta z)_eta - (x_eta z)_zeta] */
-    s[1] = 0.5 * (T(C, CZ, ETA, CX, ZETA, p) - T(C, CZ, ZETA, CX, ETA, p)
-                  + T(C, CX, ZETA, CZ, ETA, p) - T(C, CX, ETA, CZ, ZETA, p));
-    /* xi_z/J = 1/2[(x_eta y)_zeta - (x_zeta y)_eta + (x y_zeta)_eta - (x y_eta)_zeta] */
-    s[2] = 0.5 * (T(C, CX, ETA, CY, ZETA, p) - T(C, CX, ZETA, CY, ETA, p)
-                  + T(C, CY, ZETA, CX, ETA, p) - T(C, CY, ETA, CX, ZETA, p));
-    /* eta_x/J = 1/2[(y_zeta z)_xi - (y_xi z)_zeta + (y z_xi)_zeta - (y z_zeta)_xi] */
-    s[3] = 0.5 * (T(C, CY, ZETA, CZ, XI, p) - T(C, CY, XI, CZ, ZETA, p)
-                  + T(C, CZ, XI, CY, ZETA, p) - T(C, CZ, ZETA, CY, XI, p));
-    /* eta_y/J = 1/2[(x z_zeta)_xi - (x z_xi)_zeta + (x_xi z)_zeta - (x_zeta z)_xi] */
-    s[4] = 0.5 * (T(C, CZ, ZETA, CX, XI, p) - T(C, CZ, XI, CX, ZETA, p)
-                  + T(C, CX, XI, CZ, ZETA, p) - T(C, CX, ZETA, CZ, XI, p));
-    /* eta_z/J = 1/2[(x_zeta y)_xi - (x_xi y)_zeta + (x y_xi)_zeta - (x y_zeta)_xi] */
-    s[5] = 0.5 * (T(C, CX, ZETA, CY, XI, p) - T(C, CX, XI, CY, ZETA, p)
-                  + T(C, CY, XI, CX, ZETA, p) - T(C, CY, ZETA, CX, XI, p));
-    /* zeta_x/J = 1/2[(y_xi z)_eta - (y_eta z)_xi + (y z_eta)_xi - (y z_xi)_eta] */
-    s[6] = 0.5 * (T(C, CY, XI, CZ, ETA, p) - T(C, CY, ETA, CZ, XI, p)
-                  + T(C, CZ, ETA, CY, XI, p) - T(C, CZ, XI, CY, ETA, p));
-    /* zeta_y/J = 1/2[(x z_xi)_eta - (x z_eta)_xi + (x_eta z)_xi - (x_xi z)_eta] */
-    s[7] = 0.5 * (T(C, CZ, XI, CX, ETA, p) - T(C, CZ, ETA, CX, XI, p)
-                  + T(C, CX, ETA, CZ, XI, p) - T(C, CX, XI, CZ, ETA, p));
-    /* zeta_z/J = 1/2[(x_xi y)_eta - (x_eta y)_xi + (x y_eta)_xi - (x y_xi)_eta] */
-    s[8] = 0.5 * (T(C, CX, XI, CY, ETA, p) - T(C, CX, ETA, CY, XI, p)
-                  + T(C, CY, ETA, CX, XI, p) - T(C, CY, XI, CX, ETA, p));
+    for (int d = 0; d < 3; d++)
+        scmm3_dir(C, d, p, s + 3 * d);
 }
 
 /* 2D reduction of eq. (JBabc) (z = zeta, nothing depends on zeta):
@@ -204,11 +214,10 @@ static double jacobian_inv(const cgrid *C, const int p[3])
         for (int d = 0; d < 3; d++) {
             int q[3] = {p[0], p[1], p[2]};
             for (int m = -h; m <= h; m++) {
-                double s[9];
+                double s[3];
                 q[d] = p[d] + m;
-                scmm3(C, q, s);
-                w[m + h] = crd(C, CX, q) * s[3 * d + 0] + crd(C, CY, q) * s[3 * d + 1]
-                           + crd(C, CZ, q) * s[3 * d + 2];
+                scmm3_dir(C, d, q, s); /* only s_d: it has no derivative along d */
+                w[m + h] = crd(C, CX, q) * s[0] + crd(C, CY, q) * s[1] + crd(C, CZ, q) * s[2];
             }
             sum += deriv_Y(C->Y, w);
         }
@@ -288,6 +297,12 @@ int fpo_metrics(const fpo_grid *gr, int Y, const double *xyz, double *met)
                 for (int c = 0; c < L.nmet; c++)
                     met[c * L.vol + at(&L, i, j, k)] = m[c];
             }
+    /* the method needs a non-degenerate, non-folded grid: 1/J > 0 */
+    for (int k = lo[2]; k < hi[2]; k++)
+        for (int j = lo[1]; j < hi[1]; j++)
+            for (int i = lo[0]; i < hi[0]; i++)
+                if (!(met[(L.nmet - 1) * L.vol + at(&L, i, j, k)] > 0.0))
+                    return -2;
     /* periodic ghost layers hold exact copies of the periodic image */
     for (int d = 0; d < L.ndim; d++) {
         if (L.bc[d] != 0)
@@ -359,7 +374,7 @@ static void phys_flux(int ndim, double gam, const double *Q, double Fx[3][NVMAX]
  * flux Jacobian along the unit normal n = s_f/|s_f|, eigenvalues scaled by
  * sigma = |s_f| / (1/J)_f (A acts on Q~ = Q/J).  Degenerate eigenvectors use
  * the tangent t1 = normalize(n x e_a) with a = argmin |n_k| (lowest k on
- * ties) and t2 = n x t1; in 2D t = (-n_y, n_x).  Field order: u_n - c,
+ * ties within 1e-10) and t2 = n x t1; in 2D t = (-n_y, n_x).  Field order: u_n - c,
  * u_n (entropy), tangential field(s), u_n + c. */
 typedef struct {
     double R[NVMAX][NVMAX];  /* R[row][s]: column s is r_s */
@@ -442,9 +457,11 @@ static void roe_system(int ndim, double gam, const double *QL, const double *QR,
         t[0][2] = 0.0;
         nt = 1;
     } else {
+        /* components closer than 1e-10 count as tied (lowest k wins), so
+         * that grids with a symmetric normal do not depend on rounding */
         int a = 0;
         for (int c = 1; c < 3; c++)
-            if (fabs(n[c]) < fabs(n[a]))
+            if (fabs(n[c]) < fabs(n[a]) - 1e-10)
                 a = c;
         double e[3] = {0, 0, 0};
         e[a] = 1.0;
@@ -907,6 +924,72 @@ int fpo_residual_at(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
         }
         free(qline);
         free(buf);
+    }
+    return 0;
+}
+
+/* The residual at selected interior nodes with the metrics evaluated on the
+ * fly from the coordinates (no metric array): for each direction the line
+ * through the node is gathered over the reach of its two faces only. */
+int fpo_residual_at_xyz(const fpo_grid *gr, const fpo_scheme *sc, const double *xyz,
+                        const double *q, int npts, const int *ijk, double *out)
+{
+    layout L;
+    cgrid C;
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || make_cgrid(&L, sc->Y, xyz, &C) || npts < 0)
+        return -1;
+    for (int t = 0; t < npts; t++)
+        for (int d = 0; d < L.ndim; d++) {
+            int c = ijk[3 * t + d];
+            if (c < 0 || c >= L.n[d])
+                return -1;
+        }
+    /* reach of the two faces of a node: the 6-point stencil (3 nodes) and
+     * the face interpolation (Y/2 nodes); the ghost width covers both */
+    const int R = L.g;
+    const int len = 2 * R + 1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int t = 0; t < npts; t++) {
+        int p[3] = {ijk[3 * t], ijk[3 * t + 1], L.ndim == 3 ? ijk[3 * t + 2] : 0};
+        double buf[(NVMAX + 1 + 3) * 17];
+        double acc[NVMAX] = {0, 0, 0, 0, 0};
+        double Vp = 0.0;
+        for (int d = 0; d < L.ndim; d++) {
+            int nsd = L.ndim;
+            for (int m = -R; m <= R; m++) {
+                int c3[3] = {p[0], p[1], p[2]};
+                c3[d] = p[d] + m;
+                /* state: periodic image or frozen ghost value */
+                int s3[3] = {c3[0], c3[1], c3[2]};
+                if (L.bc[d] == 0)
+                    s3[d] = ((c3[d] % L.n[d]) + L.n[d]) % L.n[d];
+                long off = at(&L, s3[0], s3[1], s3[2]);
+                for (int v = 0; v < L.nv; v++)
+                    buf[v * len + m + R] = q[v * L.vol + off];
+                double mt[10];
+                metrics_node(&C, c3, mt);
+                buf[L.nv * len + m + R] = mt[L.nmet - 1];
+                for (int c = 0; c < nsd; c++)
+                    buf[(L.nv + 1 + c) * len + m + R] = mt[d * nsd + c];
+                if (m == 0)
+                    Vp = mt[L.nmet - 1];
+            }
+            line_t ln;
+            ln.ndim = L.ndim;
+            ln.nv = L.nv;
+            for (int v = 0; v < L.nv; v++)
+                ln.Q[v] = buf + v * len + R - p[d];
+            ln.V = buf + L.nv * len + R - p[d];
+            for (int c = 0; c < nsd; c++)
+                ln.S[c] = buf + (L.nv + 1 + c) * len + R - p[d];
+            double Fm[NVMAX], Fpl[NVMAX];
+            face_flux(sc, &ln, p[d] - 1, Fm);
+            face_flux(sc, &ln, p[d], Fpl);
+            for (int v = 0; v < L.nv; v++)
+                acc[v] += Fpl[v] - Fm[v];
+        }
+        for (int v = 0; v < L.nv; v++)
+            out[(long)L.nv * t + v] = -acc[v] / Vp;
     }
     return 0;
 }

@@ -19,7 +19,8 @@
  * Boundary kinds per axis: 0 = periodic (ghost layers of q are ignored and
  * taken from the periodic image), 1 = frozen (ghost layers of q are read and
  * never changed).
- * Return values: 0 on success, -1 on invalid arguments.
+ * Return values: 0 on success, -1 on invalid arguments, -2 from the metric
+ * routine when the grid is folded (1/J <= 0 somewhere).
  */
 #ifndef FPO_H
 #define FPO_H
@@ -63,6 +64,11 @@ int fpo_residual(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
 /* The residual at selected interior nodes only: out[nv*p + v]. */
 int fpo_residual_at(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
                     const double *q, int npts, const int *ijk, double *out);
+
+/* As fpo_residual_at, with the metrics of order sc->Y evaluated on the fly
+ * from the coordinates xyz instead of read from a metric array. */
+int fpo_residual_at_xyz(const fpo_grid *gr, const fpo_scheme *sc, const double *xyz,
+                        const double *q, int npts, const int *ijk, double *out);
 
 /* One step of the third-order TVD Runge-Kutta scheme, in place on the
  * interior of q. */

@@ -1,0 +1,127 @@
+// fp_inst.hip -- instantiates the sweep and face-flux kernels for one
+// (precision, reconstruction) pair, selected at compile time by FP_INST_PREC
+// (0 = FP64, 1 = mixed FP32) and FP_INST_RECON (0 = WENO5-JS, 1 = linear
+// upwind).  The build compiles this file once per pair, in parallel.
+#include "fp_kernels.hpp"
+
+#if !defined(FP_INST_PREC) || !defined(FP_INST_RECON)
+#error "FP_INST_PREC and FP_INST_RECON must be defined"
+#endif
+
+#define FP_CAT2(a, b) a##b
+#define FP_CAT(a, b) FP_CAT2(a, b)
+#define FP_SUFFIX FP_CAT(FP_CAT(_p, FP_INST_PREC), FP_CAT(_r, FP_INST_RECON))
+
+namespace fpk {
+
+namespace {
+
+constexpr int P = FP_INST_PREC;
+constexpr int R = FP_INST_RECON;
+
+inline unsigned blocks_for(long threads, int per_block) {
+    return (unsigned)((threads + per_block - 1) / per_block);
+}
+
+template <int DIM, int DIR, int Y>
+void launch_march(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
+    constexpr int OTH = DIR == 1 ? 2 : 1;
+    const long threads = (long)a.G.n[0] * a.G.n[OTH] * a.nseg[DIR];
+    hipLaunchKernelGGL((k_sweep_march<DIM, DIR, R, Y, P>), dim3(blocks_for(threads, 256)), dim3(256),
+                       0, s, a.G, a.sk, a.met, a.qs, a.qb, ep, a.S[DIR], a.nseg[DIR]);
+}
+
+template <int DIM, int Y>
+hipError_t run_stage(const SweepArgs& a, hipStream_t s) {
+    const long faces = (long)(a.G.n[0] + 1) * a.G.n[1] * a.G.n[2];
+    const long waves = (faces + 62) / 63;
+    hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, a.G,
+                       a.sk, a.met, a.qs, a.qb, a.ep_first);
+    if constexpr (DIM == 3) {
+        launch_march<3, 1, Y>(a, a.ep_mid, s);
+        launch_march<3, 2, Y>(a, a.ep_last, s);
+    } else {
+        launch_march<2, 1, Y>(a, a.ep_last, s);
+    }
+    return hipGetLastError();
+}
+
+template <int DIM, int Y>
+hipError_t run_dir(const SweepArgs& a, int dir, const EpiK& ep, hipStream_t s) {
+    if (dir == 0) {
+        const long faces = (long)(a.G.n[0] + 1) * a.G.n[1] * a.G.n[2];
+        const long waves = (faces + 62) / 63;
+        hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3(blocks_for(waves, 4)), dim3(256), 0, s,
+                           a.G, a.sk, a.met, a.qs, a.qb, ep);
+    } else if (dir == 1) {
+        launch_march<DIM, 1, Y>(a, ep, s);
+    } else if constexpr (DIM == 3) {
+        launch_march<3, 2, Y>(a, ep, s);
+    }
+    return hipGetLastError();
+}
+
+template <int DIM>
+dir_fn pick_dir(int Y) {
+    switch (Y) {
+    case 2: return &run_dir<DIM, 2>;
+    case 4: return &run_dir<DIM, 4>;
+    case 6: return &run_dir<DIM, 6>;
+    case 8: return &run_dir<DIM, 8>;
+    }
+    return nullptr;
+}
+
+template <int DIM, int DIR, int Y>
+hipError_t run_faceflux(const GeoK& G, const SchemeK& sk, const double* met, const double* q,
+                        double* out, hipStream_t s) {
+    long total = 1;
+    for (int d = 0; d < 3; ++d) total *= (long)G.n[d] + (d == DIR ? 1 : 0);
+    hipLaunchKernelGGL((k_face_flux<DIM, DIR, R, Y, P>), dim3(blocks_for(total, 256)), dim3(256), 0,
+                       s, G, sk, met, q, out);
+    return hipGetLastError();
+}
+
+template <int DIM>
+stage_fn pick_stage(int Y) {
+    switch (Y) {
+    case 2: return &run_stage<DIM, 2>;
+    case 4: return &run_stage<DIM, 4>;
+    case 6: return &run_stage<DIM, 6>;
+    case 8: return &run_stage<DIM, 8>;
+    }
+    return nullptr;
+}
+
+template <int DIM, int DIR>
+faceflux_fn pick_ff(int Y) {
+    switch (Y) {
+    case 2: return &run_faceflux<DIM, DIR, 2>;
+    case 4: return &run_faceflux<DIM, DIR, 4>;
+    case 6: return &run_faceflux<DIM, DIR, 6>;
+    case 8: return &run_faceflux<DIM, DIR, 8>;
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+stage_fn FP_CAT(get_stage, FP_SUFFIX)(int ndim, int Y) {
+    return ndim == 3 ? pick_stage<3>(Y) : pick_stage<2>(Y);
+}
+
+dir_fn FP_CAT(get_dir, FP_SUFFIX)(int ndim, int Y) {
+    return ndim == 3 ? pick_dir<3>(Y) : pick_dir<2>(Y);
+}
+
+faceflux_fn FP_CAT(get_faceflux, FP_SUFFIX)(int ndim, int dir, int Y) {
+    if (ndim == 3) {
+        if (dir == 0) return pick_ff<3, 0>(Y);
+        if (dir == 1) return pick_ff<3, 1>(Y);
+        return pick_ff<3, 2>(Y);
+    }
+    if (dir == 0) return pick_ff<2, 0>(Y);
+    return pick_ff<2, 1>(Y);
+}
+
+}  // namespace fpk

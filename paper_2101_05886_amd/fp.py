@@ -1,0 +1,259 @@
+"""Python binding of ``libfp.so`` (the C ABI declared in ``include/fp.h``).
+
+Argument marshalling only: every array is a torch float64 tensor on the
+current HIP device, passed by ``data_ptr()``; every computation runs in the
+library's gfx950 kernels on torch's current stream.  If the library is not
+built this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfp.so")
+
+FP_OK, FP_EINVAL, FP_EUNSUPPORTED, FP_EHIP, FP_ENOMEM, FP_ENONPHYS = 0, -1, -2, -3, -4, -5
+FP_WENO5JS, FP_LINUP5 = 0, 1
+FP_FP64, FP_MIXED32 = 0, 1
+FP_BC_PERIODIC, FP_BC_FROZEN = 0, 1
+
+EXPORTS = ["fp_state_bytes", "fp_metric_bytes", "fp_coord_bytes", "fp_work_bytes", "fp_metrics",
+           "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve", "fp_max_dt",
+           "fp_check_state", "fp_release_cache", "fp_last_error"]
+
+
+class FPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class FPGrid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("n", C.c_int32 * 3), ("ghost", C.c_int32),
+                ("bc", C.c_int32 * 3)]
+
+
+class FPScheme(C.Structure):
+    _fields_ = [("recon", C.c_int32), ("metric_order", C.c_int32), ("reformulated", C.c_int32),
+                ("precision", C.c_int32), ("gamma", C.c_double), ("weno_eps", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FPError(FP_EHIP, f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        gp, sp, vp, dp = C.POINTER(FPGrid), C.POINTER(FPScheme), C.c_void_p, C.c_void_p
+        for name in ("fp_state_bytes", "fp_metric_bytes", "fp_work_bytes"):
+            getattr(L, name).argtypes = [gp]
+            getattr(L, name).restype = C.c_size_t
+        L.fp_coord_bytes.argtypes = [gp, C.c_int32]
+        L.fp_coord_bytes.restype = C.c_size_t
+        L.fp_metrics.argtypes = [gp, C.c_int32, dp, dp, vp]
+        L.fp_face_fluxes.argtypes = [gp, sp, dp, dp, C.c_int32, dp, vp]
+        L.fp_residual.argtypes = [gp, sp, dp, dp, dp, vp]
+        L.fp_residual_dir.argtypes = [gp, sp, dp, dp, C.c_int32, dp, C.c_int32, vp]
+        L.fp_rk3_step.argtypes = [gp, sp, dp, dp, dp, C.c_double, vp]
+        L.fp_solve.argtypes = [gp, sp, dp, dp, dp, C.c_double, C.c_int64, vp]
+        L.fp_max_dt.argtypes = [gp, sp, dp, dp, C.c_double, dp, vp]
+        L.fp_check_state.argtypes = [gp, sp, dp, dp, vp]
+        L.fp_release_cache.argtypes = []
+        L.fp_release_cache.restype = None
+        L.fp_last_error.restype = C.c_char_p
+        for name in ("fp_metrics", "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve",
+                     "fp_max_dt", "fp_check_state"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != FP_OK:
+        raise FPError(rc, lib().fp_last_error().decode())
+
+
+class Grid:
+    """One structured block: ndim, interior nodes n, ghost width, boundary
+    kind per axis (FP_BC_PERIODIC / FP_BC_FROZEN)."""
+
+    def __init__(self, ndim, n, ghost=3, bc=None):
+        if isinstance(n, int):
+            n = [n] * ndim
+        n = [int(v) for v in n] + [1] * (3 - len(n))
+        if ndim == 2:
+            n[2] = 1
+        bc = list(bc) if bc is not None else [FP_BC_PERIODIC] * 3
+        bc = [int(b) for b in bc] + [FP_BC_PERIODIC] * (3 - len(bc))
+        self.ndim, self.n, self.ghost, self.bc = int(ndim), n, int(ghost), bc
+
+    def c(self):
+        g = FPGrid()
+        g.ndim, g.ghost = self.ndim, self.ghost
+        for d in range(3):
+            g.n[d] = self.n[d]
+            g.bc[d] = self.bc[d]
+        return g
+
+    @property
+    def nv(self):
+        return self.ndim + 2
+
+    @property
+    def nmet(self):
+        return 10 if self.ndim == 3 else 5
+
+    def state_shape(self, nv=None):
+        ext = [self.n[d] + 2 * self.ghost for d in range(self.ndim)]
+        return (self.nv if nv is None else nv,) + tuple(reversed(ext))
+
+    def metric_shape(self):
+        return self.state_shape(self.nmet)
+
+    def coord_shape(self, Y):
+        ext = [self.n[d] + 2 * (self.ghost + Y // 2) for d in range(self.ndim)]
+        return (self.ndim,) + tuple(reversed(ext))
+
+    def work_shape(self):
+        return (3,) + self.state_shape()
+
+
+class Scheme:
+    def __init__(self, recon="weno5", metric_order=6, reformulated=True, precision="fp64",
+                 gamma=1.4, weno_eps=1e-6):
+        self.recon = {"weno5": FP_WENO5JS, "linup5": FP_LINUP5}.get(recon, recon)
+        self.precision = {"fp64": FP_FP64, "mixed": FP_MIXED32}.get(precision, precision)
+        self.metric_order, self.reformulated = int(metric_order), int(bool(reformulated))
+        self.gamma, self.weno_eps = float(gamma), float(weno_eps)
+
+    def c(self):
+        s = FPScheme()
+        s.recon, s.metric_order, s.reformulated = int(self.recon), self.metric_order, self.reformulated
+        s.precision, s.gamma, s.weno_eps = int(self.precision), self.gamma, self.weno_eps
+        return s
+
+
+def _dev(t: torch.Tensor, nbytes: int, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise FPError(FP_EINVAL, f"{name} must be a float64 tensor on the GPU")
+    if not t.is_contiguous():
+        raise FPError(FP_EINVAL, f"{name} must be contiguous")
+    if t.numel() * 8 < nbytes:
+        raise FPError(FP_EINVAL, f"{name} holds {t.numel() * 8} bytes, needs {nbytes}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def state_bytes(grid: Grid) -> int:
+    g = grid.c()
+    return int(lib().fp_state_bytes(C.byref(g)))
+
+
+def metric_bytes(grid: Grid) -> int:
+    g = grid.c()
+    return int(lib().fp_metric_bytes(C.byref(g)))
+
+
+def coord_bytes(grid: Grid, Y: int) -> int:
+    g = grid.c()
+    return int(lib().fp_coord_bytes(C.byref(g), int(Y)))
+
+
+def work_bytes(grid: Grid) -> int:
+    g = grid.c()
+    return int(lib().fp_work_bytes(C.byref(g)))
+
+
+def metrics(grid: Grid, Y: int, xyz: torch.Tensor, met: torch.Tensor | None = None) -> torch.Tensor:
+    if met is None:
+        met = torch.zeros(grid.metric_shape(), dtype=torch.float64, device=xyz.device)
+    g = grid.c()
+    _check(lib().fp_metrics(C.byref(g), int(Y), _dev(xyz, coord_bytes(grid, Y), "xyz"),
+                            _dev(met, metric_bytes(grid), "met"), _stream()))
+    return met
+
+
+def face_fluxes(grid: Grid, scheme: Scheme, met, q, direction: int, out=None) -> torch.Tensor:
+    ext = list(grid.n[:grid.ndim])
+    ext[direction] += 1
+    shape = (grid.nv,) + tuple(reversed(ext))
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=q.device)
+    g, s = grid.c(), scheme.c()
+    nbytes = 8 * grid.nv
+    for e in ext:
+        nbytes *= e
+    _check(lib().fp_face_fluxes(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                                _dev(q, state_bytes(grid), "q"), int(direction),
+                                _dev(out, nbytes, "flux"), _stream()))
+    return out
+
+
+def residual(grid: Grid, scheme: Scheme, met, q, dqdt=None) -> torch.Tensor:
+    if dqdt is None:
+        dqdt = torch.zeros_like(q)
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_residual(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                             _dev(q, state_bytes(grid), "q"), _dev(dqdt, state_bytes(grid), "dqdt"),
+                             _stream()))
+    return dqdt
+
+
+def residual_dir(grid: Grid, scheme: Scheme, met, q, direction: int, acc, accumulate=False):
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_residual_dir(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                                 _dev(q, state_bytes(grid), "q"), int(direction),
+                                 _dev(acc, state_bytes(grid), "acc"), int(bool(accumulate)),
+                                 _stream()))
+    return acc
+
+
+def rk3_step(grid: Grid, scheme: Scheme, met, q, work, dt: float) -> torch.Tensor:
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_rk3_step(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                             _dev(q, state_bytes(grid), "q"), _dev(work, work_bytes(grid), "work"),
+                             float(dt), _stream()))
+    return q
+
+
+def solve(grid: Grid, scheme: Scheme, met, q, work, dt: float, nsteps: int) -> torch.Tensor:
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_solve(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                          _dev(q, state_bytes(grid), "q"), _dev(work, work_bytes(grid), "work"),
+                          float(dt), int(nsteps), _stream()))
+    return q
+
+
+def max_dt(grid: Grid, scheme: Scheme, met, q, cfl: float, out=None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=q.device)
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_max_dt(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                           _dev(q, state_bytes(grid), "q"), float(cfl), _dev(out, 8, "dt"),
+                           _stream()))
+    return out
+
+
+def check_state(grid: Grid, scheme: Scheme, q, flag=None) -> torch.Tensor:
+    if flag is None:
+        flag = torch.zeros(1, dtype=torch.int32, device=q.device)
+    if not flag.is_cuda or flag.dtype != torch.int32:
+        raise FPError(FP_EINVAL, "flag must be an int32 tensor on the GPU")
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_check_state(C.byref(g), C.byref(s), _dev(q, state_bytes(grid), "q"),
+                                C.c_void_p(flag.data_ptr()), _stream()))
+    return flag
+
+
+def release_cache() -> None:
+    lib().fp_release_cache()

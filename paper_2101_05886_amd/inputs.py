@@ -92,24 +92,25 @@ def _periodic_take(field, ndim, n, gc):
 
 def wavy_grid(ndim: int, n, L: float, g: int, Y: int, amp: float = 0.1,
               jitter: float = 0.0, seed: int = 0) -> np.ndarray:
-    """Periodic wavy grid on [-L/2, L/2)^dim with node spacing L/n.
+    """Periodic wavy grid with node spacing h = L/n[0] on every axis, axis d
+    of length L_d = n[d]*h, centred on the origin.
 
-    2D: ``x = xi + A*s(xi)*s(eta)``, ``y = eta + A*s(xi)*s(eta)``;
+    2D: ``x = xi + A*s0(xi)*s1(eta)``, ``y = eta + A*s0(xi)*s1(eta)``;
     3D: ``x = xi + P``, ``y = eta + P``, ``z = zeta + P`` with
-    ``P = A*s(xi)*s(eta)*s(zeta)``, ``s(t) = sin(2*pi*(t + L/2)/L)`` and
-    ``A = amp*L``.  Optional jitter: ``jitter*L/n`` in a random direction per
+    ``P = A*s0(xi)*s1(eta)*s2(zeta)``, ``s_d(t) = sin(2*pi*(t + L_d/2)/L_d)`` and
+    ``A = amp*min_d L_d`` (for amp = 0.1 the mapping keeps J >= 1 - 0.2*pi in
+    2D and 1 - 0.2*pi*2/sqrt(3) in 3D on any axis lengths).  Optional jitter: ``jitter*h`` in a random direction per
     unique node, carried to ghost images (periodic).  Ghost nodes are the
     mapping evaluated out of range plus the image's jitter, so
-    ``x(i + n) = x(i) + L``.
+    ``x(i + n) = x(i) + L_d``.
     """
     n3 = _n3(ndim, n)
     gc = coord_ghost(g, Y)
     h = L / n3[0]
-    if any(abs(L / n3[d] - h) > 1e-15 * L for d in range(ndim)):
-        raise ValueError("wavy_grid needs the same node count on every axis")
-    ax = [-L / 2 + np.arange(-gc, n3[d] + gc) * (L / n3[d]) for d in range(ndim)]
-    s = [np.sin(2.0 * math.pi * (a + L / 2) / L) for a in ax]
-    A = amp * L
+    Ld = [h * n3[d] for d in range(ndim)]
+    ax = [-Ld[d] / 2 + np.arange(-gc, n3[d] + gc) * h for d in range(ndim)]
+    s = [np.sin(2.0 * math.pi * (ax[d] + Ld[d] / 2) / Ld[d]) for d in range(ndim)]
+    A = amp * min(Ld)
     if ndim == 2:
         eta, xi = np.meshgrid(ax[1], ax[0], indexing="ij")
         P = A * s[1][:, None] * s[0][None, :]
@@ -123,6 +124,12 @@ def wavy_grid(ndim: int, n, L: float, g: int, Y: int, amp: float = 0.1,
         jf = _jitter_field(ndim, n3, jitter, h, rng)
         xyz = xyz + _periodic_take(jf, ndim, n3, gc)
     return np.ascontiguousarray(xyz)
+
+
+def wavy_periods(ndim: int, n, L: float):
+    """Physical period of each axis of ``wavy_grid(ndim, n, L, ...)``."""
+    n3 = _n3(ndim, n)
+    return tuple(L / n3[0] * n3[d] for d in range(ndim))
 
 
 def paper_wavy_grid_2d(n: int, g: int, Y: int, L: float = 20.0, A: float = 0.6,
@@ -174,6 +181,58 @@ def affine_grid(ndim: int, n, g: int, Y: int, A: np.ndarray, b=None) -> np.ndarr
         comp = [I, J, K]
     out = np.stack([sum(A[c, e] * comp[e] for e in range(ndim)) + b[c] for c in range(ndim)])
     return np.ascontiguousarray(out)
+
+
+def ogrid_sector_block(n, g: int, Y: int, sector: float, skew_deg: float = 0.0,
+                       rotation: float = 0.0, r_wall: float = 1.0, dr0: float = 0.01,
+                       ratio: float = 1.1, cap: int = 48) -> np.ndarray:
+    """One block of an O-grid around a cylinder of radius ``r_wall``: index i
+    runs along the (decreasing) polar angle over ``sector`` radians, j outward
+    from the wall with first spacing ``dr0`` growing by ``ratio`` per cell
+    (constant after ``cap`` cells; ghosts inside the wall keep ``dr0``), k
+    along the axis with spacing ``r_wall*dtheta``.  The angle is skewed by
+    ``tan(skew)*(r - r_wall)/r`` and the block is rotated by ``rotation``
+    about the axis.  Ghost coordinates are the mapping evaluated out of range
+    (a block with frozen ghost layers on every axis)."""
+    nt, nr, nz = (int(v) for v in n)
+    gc = coord_ghost(g, Y)
+    i = np.arange(-gc, nt + gc, dtype=np.float64)
+    jj = np.arange(-gc, nr + gc)
+    k = np.arange(-gc, nz + gc, dtype=np.float64)
+    dth = sector / nt
+    steps = dr0 * ratio ** np.minimum(np.arange(nr + gc), cap)
+    r = np.empty(jj.shape)
+    pos = jj >= 0
+    r[pos] = r_wall + np.concatenate([[0.0], np.cumsum(steps)])[jj[pos]]
+    r[~pos] = r_wall + jj[~pos] * dr0
+    th0 = 0.5 * sector
+    K, J, Ii = np.meshgrid(k, r, i, indexing="ij")
+    theta = th0 - Ii * dth + math.tan(math.radians(skew_deg)) * (J - r_wall) / J
+    x = J * np.cos(theta + rotation)
+    y = J * np.sin(theta + rotation)
+    z = K * (r_wall * dth)
+    return np.ascontiguousarray(np.stack([x, y, z]))
+
+
+@dataclass
+class BlockSpec:
+    n: tuple
+    sector: float
+    skew_deg: float
+    rotation: float
+
+
+def multiblock_specs(nblocks: int = 48, seed: int = 4):
+    """Seeded uneven O-grid sector blocks: n_theta ~ U{32..192},
+    n_r ~ U{32..128}, n_z ~ U{16..64}, sector ~ U(pi/3, pi),
+    skew ~ U(0, 30) degrees, rotation ~ U(0, 2 pi)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(nblocks):
+        n = (int(rng.integers(32, 193)), int(rng.integers(32, 129)), int(rng.integers(16, 65)))
+        out.append(BlockSpec(n, float(rng.uniform(math.pi / 3, math.pi)),
+                             float(rng.uniform(0.0, 30.0)), float(rng.uniform(0.0, 2 * math.pi))))
+    return out
 
 
 def state_nodes(xyz: np.ndarray, g: int, Y: int) -> np.ndarray:
@@ -233,15 +292,17 @@ class Vortex:
 
     def primitives(self, x, y, t=0.0, period=None):
         """(rho, u, v, p) at points (x, y) and time t (centre translated by
-        the background velocity; nearest periodic image if ``period``)."""
+        the background velocity; nearest periodic image if ``period``, a
+        scalar or the (x, y) periods)."""
         g = self.gamma
         cx = self.center[0] + self.vel_inf[0] * t
         cy = self.center[1] + self.vel_inf[1] * t
         dx = x - cx
         dy = y - cy
         if period is not None:
-            dx = dx - period * np.round(dx / period)
-            dy = dy - period * np.round(dy / period)
+            px, py = (period, period) if np.isscalar(period) else (period[0], period[1])
+            dx = dx - px * np.round(dx / px)
+            dy = dy - py * np.round(dy / py)
         r = np.sqrt(dx * dx + dy * dy)
         tau = r / self.rc
         ex = np.exp(self.alpha * (1.0 - tau * tau))

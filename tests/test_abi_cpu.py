@@ -1,0 +1,71 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol include/fp.h
+declares, sizes arrays as documented, and rejects invalid arguments before
+enqueueing anything (no compute call is made here: there is no GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2101_05886_amd import fp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "fp.h")).read()
+    return sorted(set(re.findall(r"\b(fp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == sorted(fp.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = fp.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_sizes():
+    g = fp.Grid(3, (10, 12, 14), 3)
+    n = (16 * 18 * 20)
+    assert fp.state_bytes(g) == 8 * 5 * n
+    assert fp.metric_bytes(g) == 8 * 10 * n
+    assert fp.work_bytes(g) == 3 * 8 * 5 * n
+    assert fp.coord_bytes(g, 6) == 8 * 3 * (22 * 24 * 26)  # ghost 3 + 3 per side
+    g2 = fp.Grid(2, (10, 12), 4)
+    assert fp.state_bytes(g2) == 8 * 4 * 18 * 20
+    assert fp.coord_bytes(g2, 8) == 8 * 2 * 26 * 28
+
+
+def _call_residual(grid, scheme):
+    L = fp.lib()
+    g, s = grid.c(), scheme.c()
+    dummy = C.c_void_p(16)  # never dereferenced: validation fails first
+    return L.fp_residual(C.byref(g), C.byref(s), dummy, dummy, dummy, None)
+
+
+@pytest.mark.parametrize("grid,scheme,status", [
+    (fp.Grid(4, (8, 8, 8), 3), fp.Scheme(), fp.FP_EINVAL),
+    (fp.Grid(3, (8, 8, 8), 2), fp.Scheme(), fp.FP_EINVAL),
+    (fp.Grid(3, (8, 0, 8), 3), fp.Scheme(), fp.FP_EINVAL),
+    (fp.Grid(3, (2, 8, 8), 3), fp.Scheme(), fp.FP_EINVAL),          # periodic n < ghost
+    (fp.Grid(3, (8, 8, 8), 3), fp.Scheme(metric_order=5), fp.FP_EUNSUPPORTED),
+    (fp.Grid(3, (8, 8, 8), 3), fp.Scheme(metric_order=8), fp.FP_EINVAL),  # ghost < 4
+    (fp.Grid(3, (8, 8, 8), 3), fp.Scheme(gamma=1.0), fp.FP_EINVAL),
+    (fp.Grid(3, (8, 8, 8), 3), fp.Scheme(weno_eps=0.0), fp.FP_EINVAL),
+    (fp.Grid(3, (8, 8, 8), 3), fp.Scheme(precision=7), fp.FP_EINVAL),
+    (fp.Grid(3, (8, 8, 8), 3, bc=[0, 2, 0]), fp.Scheme(), fp.FP_EINVAL),
+])
+def test_invalid_arguments_rejected(grid, scheme, status):
+    assert _call_residual(grid, scheme) == status
+    assert fp.lib().fp_last_error()
+
+
+def test_null_arrays_rejected():
+    L = fp.lib()
+    g, s = fp.Grid(3, (8, 8, 8), 3).c(), fp.Scheme().c()
+    assert L.fp_residual(C.byref(g), C.byref(s), None, None, None, None) == fp.FP_EINVAL
+    assert L.fp_rk3_step(C.byref(g), C.byref(s), None, None, None, 0.1, None) == fp.FP_EINVAL
+    assert L.fp_metrics(C.byref(g), 6, None, None, None) == fp.FP_EINVAL

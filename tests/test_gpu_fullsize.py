@@ -1,0 +1,144 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times.
+
+* 2D free stream, 64^2 jittered wavy grid, WENO5-JS with second-order
+  metrics: 100 RK3 steps, GPU against the oracle step for step.
+* 3D isentropic vortex, 128^3 wavy grid, linear upwind with sixth-order
+  metrics: one full RK3 step against the oracle (every node).
+* 3D 256^3 jittered wavy grid, vortex in a Mach 0.8 flow, WENO5-JS with
+  sixth-order metrics: the residual at sampled nodes (corners and random
+  interior nodes) against the oracle evaluated node by node from the
+  coordinates (the oracle uses no GPU output).
+
+Tolerances.  The symmetric conservative metrics difference products of
+coordinates (size |x|) into metrics of size h^2 (h the node spacing), so two
+evaluation orders agree to a few hundred ulps of |x|*h: the metric bar is
+1e-13*max|x|/h relative to the metric vector.  The state after an RK3 step
+(or stage) must agree to 1e-12 relative to max|Q| when both sides get the
+same inputs (state and metrics); at sampled nodes the first stage's
+increment dt*L(Q) is compared on that scale.  Run end to end, each side with
+its own metrics, a step amplifies the metric difference about ten-fold, so
+that comparison is bounded by 20x the metric bar.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2101_05886_amd import fp
+from paper_2101_05886_amd import inputs as I
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def interior(a, g, ndim):
+    return a[(slice(None),) + (slice(g, -g),) * ndim]
+
+
+def metric_tol(xyz, n, L):
+    return 1e-13 * np.abs(xyz).max() / (L / n)
+
+
+def relerr(a, b):
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return max(np.abs(a[v] - b[v]).max() / np.abs(b[v]).max() for v in range(a.shape[0]))
+
+
+def test_c1_free_stream_100_steps_step_for_step():
+    n, Y, g = 64, 2, 3
+    xyz = I.wavy_grid(2, n, 20.0, g, Y, amp=0.1, jitter=0.05, seed=1)
+    vel = I.mach_velocity(0.5, [math.cos(math.radians(20)), math.sin(math.radians(20))])
+    q = I.uniform_state(2, n, g, 1.4, vel, 1.0)
+    og, fg = O.Grid(2, n, g), fp.Grid(2, n, g)
+    met = O.metrics(og, Y, xyz)
+    osc, fsc = O.Scheme("weno5", Y, True), fp.Scheme("weno5", Y, True)
+    dt = O.max_dt(og, osc, met, q, 0.5)
+    mg = fp.metrics(fg, Y, dev(xyz))
+    assert np.abs(host(mg) - met).max() <= metric_tol(xyz, n, 20.0) * np.abs(met).max()
+    qg = dev(q)
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    qo = q.copy()
+    worst = 0.0
+    for step in range(100):
+        fp.rk3_step(fg, fsc, mg, qg, work, dt)
+        qo = O.rk3_step(og, osc, met, qo, dt)
+        if step % 10 == 9:
+            worst = max(worst, relerr(interior(host(qg), g, 2), interior(qo, g, 2)))
+    assert worst <= 1e-12
+    out = host(qg)
+    v = interior(out, g, 2)[2] / interior(out, g, 2)[0]
+    assert np.abs(v - vel[1]).max() < 1e-13
+
+
+@pytest.mark.parametrize("Y", [2, 6])
+def test_c2_vortex_128_full_rk3_step(Y):
+    n, g, L = 128, 3, 12.0
+    xyz = I.wavy_grid(3, n, L, g, Y, amp=0.1)
+    vel = 0.5 * I.direction_3d()
+    q = I.Vortex(vel_inf=tuple(vel)).state(I.state_nodes(xyz, g, Y), period=L)
+    og, fg = O.Grid(3, n, g), fp.Grid(3, n, g)
+    met = O.metrics(og, Y, xyz)
+    osc, fsc = O.Scheme("linup5", Y, True), fp.Scheme("linup5", Y, True)
+    dt = O.max_dt(og, osc, met, q, 0.5)
+    mg = fp.metrics(fg, Y, dev(xyz))
+    assert np.abs(host(mg) - met).max() <= metric_tol(xyz, n, L) * np.abs(met).max()
+    ref = O.rk3_step(og, osc, met, q, dt)
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    # the step itself, same inputs on both sides
+    qg = dev(q)
+    fp.rk3_step(fg, fsc, dev(met), qg, work, dt)
+    assert relerr(interior(host(qg), g, 3), interior(ref, g, 3)) <= 1e-12
+    # end to end with the GPU's own metrics: a step amplifies a relative
+    # metric perturbation about ten-fold here, so the metric bar sets this one
+    qg = dev(q)
+    fp.rk3_step(fg, fsc, mg, qg, work, dt)
+    assert relerr(interior(host(qg), g, 3), interior(ref, g, 3)) <= 20 * metric_tol(xyz, n, L)
+
+
+def test_c3_256_sampled_residual_and_metrics():
+    n, g, Y, L = 256, 3, 6, 12.0
+    xyz = I.wavy_grid(3, n, L, g, Y, amp=0.1, jitter=0.05, seed=3)
+    vel = I.mach_velocity(0.8, I.direction_3d())
+    q = I.Vortex(vel_inf=tuple(vel)).state(I.state_nodes(xyz, g, Y), period=L)
+    og, fg = O.Grid(3, n, g), fp.Grid(3, n, g)
+    pts = G.sample_nodes([n] * 3, 3, 56, seed=7)
+    mg = fp.metrics(fg, Y, dev(xyz))
+    ref_m = O.metrics_at(og, Y, xyz, pts)
+    met_h = host(mg)
+    got_m = np.array([met_h[:, g + p[2], g + p[1], g + p[0]] for p in pts])
+    tol = metric_tol(xyz, n, L)
+    for d in range(3):
+        sc = np.abs(ref_m[:, 3 * d:3 * d + 3]).max()
+        assert np.abs(got_m[:, 3 * d:3 * d + 3] - ref_m[:, 3 * d:3 * d + 3]).max() <= tol * sc
+    assert np.abs(got_m[:, 9] - ref_m[:, 9]).max() <= tol * np.abs(ref_m[:, 9]).max()
+    del met_h
+    qg = dev(q)
+    r = host(fp.residual(fg, fp.Scheme("weno5", Y, True), mg, qg))
+    got = np.array([r[:, g + p[2], g + p[1], g + p[0]] for p in pts])
+    del r
+    ref = O.residual_at_xyz(og, O.Scheme("weno5", Y, True), xyz, q, pts)
+    # CFL 0.5 step from the oracle metrics at the sampled nodes
+    speed = 0.0
+    for p, m in zip(pts, ref_m):
+        Qp = q[:, g + p[2], g + p[1], g + p[0]]
+        u = Qp[1:4] / Qp[0]
+        c = math.sqrt(1.4 * 0.4 * (Qp[4] - 0.5 * Qp[0] * u @ u) / Qp[0])
+        speed = max(speed, sum(abs(m[3 * d:3 * d + 3] @ u) + c * np.linalg.norm(m[3 * d:3 * d + 3])
+                               for d in range(3)) / m[9])
+    dt = 0.5 / speed
+    # end to end (each side its own metrics): bounded by the metric bar
+    qscale = np.abs(q.reshape(5, -1)).max(axis=1)
+    assert np.all(dt * np.abs(got - ref).max(axis=0) <= max(1e-12, 20 * tol) * qscale)

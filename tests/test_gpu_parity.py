@@ -1,0 +1,274 @@
+"""GPU parity: the gfx950 library (through its C ABI) against the FP64 oracle
+on the same seeded inputs.
+
+Bar (FP64 path): per variable, max |gpu - oracle| / max |oracle| <= 1e-12 for
+face fluxes, residuals and one RK3 step; metrics <= 1e-13.  The mixed path is
+checked against the oracle by the free-stream residual (round-off) and by a
+bound on the relative difference of the residual.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2101_05886_amd import fp
+from paper_2101_05886_amd import inputs as I
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "these tests need the MI355X"
+    fp.lib()  # the HIP library must be built and loadable
+    yield
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def grids(case):
+    og = O.Grid(case["ndim"], case["n"], case["g"], bc=case["bc"])
+    fg = fp.Grid(case["ndim"], case["n"], case["g"], bc=case["bc"])
+    return og, fg
+
+
+def relerr(a, b):
+    """per-variable max |a-b| / max |b|, maximised over variables"""
+    a = a.reshape(a.shape[0], -1)
+    b = b.reshape(b.shape[0], -1)
+    return max(np.abs(a[v] - b[v]).max() / max(np.abs(b[v]).max(), 1e-300) for v in range(a.shape[0]))
+
+
+def interior(a, g, ndim):
+    return a[(slice(None),) + (slice(g, -g),) * ndim]
+
+
+METRIC_CASES = [(2, (70, 45), 2), (2, (70, 45), 4), (2, (33, 64), 6), (2, (40, 40), 8),
+                (3, (21, 18, 16), 2), (3, (17, 20, 13), 6), (3, (16, 16, 16), 8)]
+
+
+@pytest.mark.parametrize("ndim,n,Y", METRIC_CASES)
+def test_metrics_periodic(ndim, n, Y):
+    case = G.periodic_case(ndim, n, Y)
+    og, fg = grids(case)
+    ref = O.metrics(og, Y, case["xyz"])
+    got = host(fp.metrics(fg, Y, dev(case["xyz"])))
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("Y", [2, 6, 8])
+def test_metrics_frozen_ogrid(Y):
+    case = G.frozen_case((37, 26, 11), Y)
+    og, fg = grids(case)
+    ref = O.metrics(og, Y, case["xyz"])
+    got = host(fp.metrics(fg, Y, dev(case["xyz"])))
+    # per direction, relative to that direction's metric vector (some
+    # components of an extruded block vanish analytically)
+    for d in range(3):
+        scale = np.abs(ref[3 * d:3 * d + 3]).max()
+        for c in range(3 * d, 3 * d + 3):
+            assert np.abs(got[c] - ref[c]).max() <= 1e-12 * scale, c
+    assert np.abs(got[9] - ref[9]).max() <= 1e-12 * np.abs(ref[9]).max()
+
+
+FLUX_CASES = [
+    # ndim, n, Y, recon, reform, state
+    (2, (70, 45), 2, "weno5", 1, "vortex"),
+    (2, (70, 45), 6, "linup5", 1, "vortex"),
+    (2, (33, 64), 4, "weno5", 0, "noisy"),
+    (2, (40, 40), 8, "weno5", 1, "noisy"),
+    (3, (21, 18, 16), 2, "weno5", 1, "vortex"),
+    (3, (17, 20, 13), 6, "linup5", 1, "noisy"),
+    (3, (16, 16, 16), 8, "weno5", 1, "vortex"),
+    (3, (19, 16, 15), 4, "weno5", 0, "noisy"),
+]
+
+
+def _ids(c):
+    return f"{c[0]}d-{'x'.join(map(str, c[1]))}-M{c[2]}-{c[3]}-{'fp' if c[4] else 'std'}-{c[5]}"
+
+
+@pytest.mark.parametrize("ndim,n,Y,recon,reform,state", FLUX_CASES, ids=[_ids(c) for c in FLUX_CASES])
+def test_face_fluxes_and_residual(ndim, n, Y, recon, reform, state):
+    case = G.periodic_case(ndim, n, Y, state=state)
+    og, fg = grids(case)
+    met = O.metrics(og, Y, case["xyz"])
+    osc = O.Scheme(recon, Y, bool(reform))
+    fsc = fp.Scheme(recon, Y, bool(reform))
+    mg, qg = dev(met), dev(case["q"])
+    for d in range(ndim):
+        ref = O.face_fluxes(og, osc, met, case["q"], d)
+        got = host(fp.face_fluxes(fg, fsc, mg, qg, d))
+        assert relerr(got, ref) <= 1e-12, f"direction {d}"
+    ref = O.residual(og, osc, met, case["q"])
+    got = host(fp.residual(fg, fsc, mg, qg))
+    g = case["g"]
+    assert relerr(interior(got, g, ndim), interior(ref, g, ndim)) <= 1e-11
+
+
+RK_CASES = [(2, (70, 45), 2, "weno5"), (2, (64, 64), 6, "linup5"), (3, (21, 18, 16), 6, "weno5"),
+            (3, (20, 20, 20), 2, "linup5")]
+
+
+@pytest.mark.parametrize("ndim,n,Y,recon", RK_CASES)
+def test_rk3_step(ndim, n, Y, recon):
+    case = G.periodic_case(ndim, n, Y)
+    og, fg = grids(case)
+    met = O.metrics(og, Y, case["xyz"])
+    osc, fsc = O.Scheme(recon, Y, True), fp.Scheme(recon, Y, True)
+    dt = 0.5 * O.max_dt(og, osc, met, case["q"], 1.0)
+    ref = O.rk3_step(og, osc, met, case["q"], dt)
+    qg = dev(case["q"])
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    fp.rk3_step(fg, fsc, dev(met), qg, work, dt)
+    got = host(qg)
+    g = case["g"]
+    assert relerr(interior(got, g, ndim), interior(ref, g, ndim)) <= 1e-12
+    # only the interior is written
+    assert np.array_equal(got[:, :g], case["q"][:, :g])
+
+
+def test_solve_graph_matches_steps_and_oracle():
+    case = G.periodic_case(2, (48, 40), 4)
+    og, fg = grids(case)
+    met = O.metrics(og, 4, case["xyz"])
+    osc, fsc = O.Scheme("weno5", 4, True), fp.Scheme("weno5", 4, True)
+    dt = 0.5 * O.max_dt(og, osc, met, case["q"], 1.0)
+    mg = dev(met)
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    q1 = dev(case["q"])
+    for _ in range(6):
+        fp.rk3_step(fg, fsc, mg, q1, work, dt)
+    q2 = dev(case["q"])
+    fp.solve(fg, fsc, mg, q2, work, dt, 4)   # captures the step graph
+    fp.solve(fg, fsc, mg, q2, work, dt, 2)   # replays it
+    a, b = host(q1), host(q2)
+    assert np.array_equal(a, b)
+    ref = O.solve(og, osc, met, case["q"], dt, 6)
+    assert relerr(interior(a, 3, 2), interior(ref, 3, 2)) <= 1e-11
+
+
+def test_frozen_block_residual_and_step():
+    case = G.frozen_case((41, 29, 12), 6, perturb=0.05)
+    og, fg = grids(case)
+    met = O.metrics(og, 6, case["xyz"])
+    osc, fsc = O.Scheme("weno5", 6, True), fp.Scheme("weno5", 6, True)
+    mg, qg = dev(met), dev(case["q"])
+    ref = O.residual(og, osc, met, case["q"])
+    got = host(fp.residual(fg, fsc, mg, qg))
+    assert relerr(interior(got, 3, 3), interior(ref, 3, 3)) <= 1e-11
+    dt = 0.5 * O.max_dt(og, osc, met, case["q"], 1.0)
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    fp.rk3_step(fg, fsc, mg, qg, work, dt)
+    refq = O.rk3_step(og, osc, met, case["q"], dt)
+    gotq = host(qg)
+    assert relerr(interior(gotq, 3, 3), interior(refq, 3, 3)) <= 1e-12
+    # frozen ghost layers are never written
+    assert np.array_equal(gotq[:, :3], case["q"][:, :3])
+    assert np.array_equal(gotq[:, :, :, -3:], case["q"][:, :, :, -3:])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("recon", ["weno5", "linup5"])
+def test_free_stream_preserved_on_gpu(prec, recon):
+    # C1 shape: 64^2 wavy grid, 5% jitter, second-order metrics, 100 RK3 steps
+    case = G.periodic_case(2, 64, 2, state="uniform", L=20.0)
+    og, fg = grids(case)
+    met = O.metrics(og, 2, case["xyz"])
+    osc = O.Scheme(recon, 2, True)
+    dt = O.max_dt(og, osc, met, case["q"], 0.5)
+    mg, qg = dev(met), dev(case["q"])
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    fp.solve(fg, fp.Scheme(recon, 2, True, precision=prec), mg, qg, work, dt, 100)
+    out = host(qg)
+    dev_ = np.abs(interior(out, 3, 2) - interior(case["q"], 3, 2)).max() / np.abs(case["q"]).max()
+    assert dev_ < 1e-13
+    # the standard scheme departs from the free stream
+    q0 = dev(case["q"])
+    fp.solve(fg, fp.Scheme(recon, 2, False, precision=prec), mg, q0, work, dt, 100)
+    out0 = host(q0)
+    assert np.abs(interior(out0, 3, 2) - interior(case["q"], 3, 2)).max() > 1e-5
+
+
+def test_free_stream_frozen_ogrid_mixed_and_fp64():
+    case = G.frozen_case((64, 48, 24), 6)
+    og, fg = grids(case)
+    mg = fp.metrics(fg, 6, dev(case["xyz"]))
+    qg = dev(case["q"])
+    for prec in ("fp64", "mixed"):
+        r = host(fp.residual(fg, fp.Scheme("weno5", 6, True, precision=prec), mg, qg))
+        met = host(mg)
+        scale = np.abs(case["q"]).max() * np.abs(met[:9]).max() / interior(met, 3, 3)[9].min()
+        assert np.abs(interior(r, 3, 3)).max() < 1e-14 * scale, prec
+
+
+def test_mixed_precision_residual_close_to_fp64_oracle():
+    case = G.periodic_case(3, (24, 20, 18), 6)
+    og, fg = grids(case)
+    met = O.metrics(og, 6, case["xyz"])
+    ref = O.residual(og, O.Scheme("weno5", 6, True), met, case["q"])
+    got = host(fp.residual(fg, fp.Scheme("weno5", 6, True, precision="mixed"), dev(met),
+                           dev(case["q"])))
+    err = relerr(interior(got, 3, 3), interior(ref, 3, 3))
+    assert err < 1e-4
+
+
+def test_deterministic_bitwise():
+    case = G.periodic_case(3, (20, 18, 16), 6, state="noisy")
+    og, fg = grids(case)
+    mg = fp.metrics(fg, 6, dev(case["xyz"]))
+    qg = dev(case["q"])
+    sc = fp.Scheme("weno5", 6, True)
+    a = host(fp.residual(fg, sc, mg, qg))
+    b = host(fp.residual(fg, sc, mg, qg))
+    assert np.array_equal(a, b)
+
+
+def test_max_dt_and_check_state():
+    case = G.periodic_case(3, (20, 18, 16), 4)
+    og, fg = grids(case)
+    met = O.metrics(og, 4, case["xyz"])
+    ref = O.max_dt(og, O.Scheme("weno5", 4, True), met, case["q"], 0.5)
+    got = float(host(fp.max_dt(fg, fp.Scheme("weno5", 4, True), dev(met), dev(case["q"]), 0.5))[0])
+    assert got == pytest.approx(ref, rel=1e-13)
+    sc = fp.Scheme("weno5", 4, True)
+    assert int(host(fp.check_state(fg, sc, dev(case["q"])))[0]) == 0
+    bad = case["q"].copy()
+    bad[4, 3 + 5, 3 + 6, 3 + 7] = -1.0  # negative energy -> negative pressure
+    assert int(host(fp.check_state(fg, sc, dev(bad)))[0]) == 1
+    bad = case["q"].copy()
+    bad[1, 3 + 2, 3 + 2, 3 + 2] = np.nan
+    assert int(host(fp.check_state(fg, sc, dev(bad)))[0]) == 1
+
+
+@pytest.mark.parametrize("ndim,n", [(2, (3, 3)), (2, (200, 3)), (3, (3, 4, 5)), (3, (65, 3, 7))])
+def test_small_and_ragged_grids(ndim, n):
+    case = G.periodic_case(ndim, n, 2, state="noisy")
+    og, fg = grids(case)
+    met = O.metrics(og, 2, case["xyz"])
+    assert np.abs(host(fp.metrics(fg, 2, dev(case["xyz"]))) - met).max() <= 1e-13 * np.abs(met).max()
+    ref = O.residual(og, O.Scheme("weno5", 2, True), met, case["q"])
+    got = host(fp.residual(fg, fp.Scheme("weno5", 2, True), dev(met), dev(case["q"])))
+    assert relerr(interior(got, 3, ndim), interior(ref, 3, ndim)) <= 1e-11
+
+
+def test_invalid_arguments_enqueue_nothing():
+    fg = fp.Grid(3, (8, 8, 8), 3)
+    q = torch.zeros(fg.state_shape(), dtype=torch.float64, device="cuda")
+    met = torch.zeros(fg.metric_shape(), dtype=torch.float64, device="cuda")
+    with pytest.raises(fp.FPError) as e:
+        fp.residual(fg, fp.Scheme("weno5", 3, True), met, q)
+    assert e.value.status == fp.FP_EUNSUPPORTED
+    with pytest.raises(fp.FPError) as e:
+        fp.residual(fp.Grid(3, (8, 8, 8), 3), fp.Scheme("weno5", 8, True), met, q)
+    assert e.value.status == fp.FP_EINVAL
+    with pytest.raises(fp.FPError):
+        fp.residual(fg, fp.Scheme("weno5", 6, True), met, q[:, :2].contiguous())

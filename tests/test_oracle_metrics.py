@@ -188,3 +188,12 @@ def test_metrics_3d_of_extruded_2d_grid_reduce_to_2d():
         assert np.abs(m3[c3, k]).max() < 1e-13
     assert np.allclose(m3[8, k], m2[4], rtol=1e-13, atol=1e-14)
     assert np.allclose(m3[9, k] / hz, m2[4], rtol=1e-13, atol=1e-14)
+
+
+def test_folded_grid_is_rejected():
+    # x = xi + A sin(2 pi xi / n) with A 2 pi / n > 1 folds the grid (x_xi < 0)
+    n, g, Y = 16, 3, 2
+    xyz = I.cartesian_grid(2, n, g, Y)
+    xyz[0] = xyz[0] + 4.0 * np.sin(2 * np.pi * xyz[0] / n)
+    with pytest.raises(ValueError):
+        O.metrics(O.Grid(2, n, g), Y, xyz)

@@ -246,3 +246,21 @@ def test_residual_at_matches_full_residual():
     ra = O.residual_at(gr, sc, met, q, pts)
     for p, v in zip(pts, ra):
         assert np.array_equal(v, r[:, g + p[2], g + p[1], g + p[0]])
+
+
+@pytest.mark.parametrize("ndim,bc", [(3, [0, 0, 0]), (2, [0, 0, 0]), (3, [1, 0, 1])])
+def test_residual_at_xyz_matches_full_residual(ndim, bc):
+    Y, g, n, L = 4, 3, 9, 12.0
+    xyz = I.wavy_grid(ndim, n, L, g, Y, amp=0.1, jitter=0.05, seed=16)
+    gr = O.Grid(ndim, n, g, bc=bc)
+    met = O.metrics(gr, Y, xyz)
+    q = I.Vortex(vel_inf=(0.4, 0.2, 0.1)).state(I.state_nodes(xyz, g, Y), period=L)
+    sc = O.Scheme("weno5", Y, True)
+    r = O.residual(gr, sc, met, q)
+    pts = np.array([[0, 0, 0], [n - 1, 2, 5], [4, n - 1, 0], [3, 3, n - 1]])
+    if ndim == 2:
+        pts[:, 2] = 0
+    ra = O.residual_at_xyz(gr, sc, xyz, q, pts)
+    for p, v in zip(pts, ra):
+        ref = r[:, g + p[2], g + p[1], g + p[0]] if ndim == 3 else r[:, g + p[1], g + p[0]]
+        assert np.allclose(v, ref, rtol=0, atol=1e-12 * np.abs(r).max())
