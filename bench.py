@@ -36,11 +36,36 @@ PEAK_FP32_TFLOPS = 157.3
 # 3D: (160 + 2*200)/3 = 186.7 B, 2D: (104 + 2*136)/3 = 125.3 B.
 STAGE_BYTES = {3: 560.0 / 3.0, 2: 376.0 / 3.0}
 
-# FP64 (or FP32) floating-point operations per face evaluation of one sweep,
-# counted from the kernels' instruction mix (add/mul/transcendental = 1,
-# fma = 2) with rocprofv3 PMC counters; see the design notes.
-FLOPS_PER_FACE = {("linup5", 3, "fp64"): 1785, ("weno5", 3, "fp64"): None,
-                  ("weno5", 3, "mixed"): None, ("weno5", 2, "fp64"): None}
+# Floating-point operations per face evaluation of each face kernel, counted
+# from the kernels' instruction mix with rocprofv3 PMC counters (add, mul,
+# transcendental = 1, fma = 2; FP64 plus FP32): profiles/flops_per_face.json,
+# written from the counter summaries in profiles/.
+FLOPS_FILE = os.path.join(ROOT, "profiles", "flops_per_face.json")
+# HBM bytes per launch of the sweep kernels from FETCH_SIZE / WRITE_SIZE
+# counter runs scaled by a plain copy kernel: profiles/hbm_traffic.json.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def csrc_hash():
+    """hash of the kernel sources; counter tables carry the hash they were
+    taken with, and a table taken on other sources is reported as stale"""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2101_05886_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_table(path):
+    try:
+        with open(path) as f:
+            table = json.load(f)
+    except (OSError, ValueError):
+        return {}, False
+    return table, table.get("csrc_sha256") == csrc_hash()
 
 WORKLOADS = {
     "c2": dict(name="3D isentropic vortex (strength 5, radius 1), 128^3 periodic wavy grid "
@@ -102,6 +127,20 @@ def cpu_baseline(w, xyz, q, g, budget_s=20.0):
                       f"FP64 oracle (gcc -O2, OpenMP over grid lines), {el:.1f} s"}
 
 
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration(torch):
+    """A plain copy kernel of known size: every launch reads and writes
+    COPY_BYTES of HBM once (the arrays are far larger than the L2 and MALL)."""
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +149,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -117,6 +159,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     from paper_2101_05886_amd import fp
 
     w = WORKLOADS[args.workload]
@@ -150,8 +196,12 @@ def main():
     torch.cuda.synchronize()
     healthy = int(flag.item()) == 0
 
-    # per-kernel timing of the direction sweeps (one kernel per call)
+    # per-kernel timing of the three sweep kernels an RK stage runs, one
+    # kernel per call with the stage's launch configuration (fp_residual_dir
+    # launches exactly the stage's kernel of that direction), HIP events on
+    # torch's current stream, which is the stream the kernels are launched on
     acc = torch.zeros_like(qg)
+    names = ["k_sweep_x", "k_sweep_wg<eta>", "k_sweep_wg<zeta>"]
     kt = {}
     for d in range(ndim):
         fp.residual_dir(G, S, met, qg, d, acc, accumulate=d > 0)
@@ -164,18 +214,23 @@ def main():
         torch.cuda.synchronize()
         kt[d] = a.elapsed_time(b) / args.kernel_reps
     dom = max(kt, key=kt.get)
-    kname = ["k_sweep_x", "k_sweep_march<eta>", "k_sweep_march<zeta>"][dom]
-    fpf = FLOPS_PER_FACE.get((w["recon"], ndim, w["prec"]))
+    ftab, fcur = counter_table(FLOPS_FILE)
+    ttab, tcur = counter_table(TRAFFIC_FILE)
+    fpf = ftab.get(f"{w['recon']}/{ndim}d/{w['prec']}")
+    traffic = ttab.get(f"{args.workload}/{names[dom]}") if tcur else None
     peak = PEAK_FP64_TFLOPS if w["prec"] == "fp64" else PEAK_FP32_TFLOPS
+    # algorithmic units of one launch: one face per node (periodic lines)
     if fpf:
         achieved = fpf * nodes / (kt[dom] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": kname,
-                "kernel_ms": kt[dom], "flops_per_face": fpf}
+                "frac": achieved / peak, "traffic": traffic}
     else:
         roof = {"bound": "alu", "achieved": None, "peak": peak, "unit": "TFLOP/s", "frac": None,
-                "traffic": None, "kernel": kname, "kernel_ms": kt[dom], "flops_per_face": None}
-    roof["sweep_ms"] = [round(kt[d], 4) for d in range(ndim)]
+                "traffic": traffic}
+    roof.update({"kernel": names[dom], "kernel_ms": kt[dom], "flops_per_face": fpf,
+                 "counters_current": fcur,
+                 "traffic_gbs": traffic / (kt[dom] * 1e-3) / 1e9 if traffic else None,
+                 "kernel_ms_by_dir": [round(kt[d], 4) for d in range(ndim)]})
     stage_gbs = STAGE_BYTES[ndim] * value / 1e9
     out = {
         "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",

@@ -101,7 +101,9 @@ size_t fp_state_bytes(const fp_grid *grid);
 size_t fp_metric_bytes(const fp_grid *grid);
 size_t fp_coord_bytes(const fp_grid *grid, int32_t metric_order);
 /* Workspace of fp_rk3_step / fp_solve: three state-sized arrays (two RK
- * stage registers and the residual accumulator). */
+ * stage registers and the residual accumulator).  When an axis is frozen,
+ * each step first copies the frozen ghost layers of q into the two stage
+ * registers. */
 size_t fp_work_bytes(const fp_grid *grid);
 
 /* Symmetric conservative metrics and 1/J of order Y (Sec. 2.1, eqs. JBabc and

@@ -79,7 +79,8 @@ fp_status check_grid(const fp_grid* g) {
     if (g->ndim == 2 && g->n[2] != 1) return fail(FP_EINVAL, "2D grids need n[2] == 1");
     long long tot = 1;
     for (int d = 0; d < g->ndim; ++d) tot *= (long long)(g->n[d] + 2 * g->ghost);
-    if (tot > (1ll << 40)) return fail(FP_EINVAL, "grid too large");
+    // the kernels address one variable array with 32-bit byte offsets
+    if (tot >= (1ll << 29)) return fail(FP_EINVAL, "grid too large: at most 2^29 nodes per block, ghosts included");
     return FP_OK;
 }
 
@@ -124,20 +125,32 @@ SchemeK make_sk(const fp_scheme* s) {
     return k;
 }
 
-// segments of the marching sweeps: enough lanes to fill the chip, each
-// segment at least 8 faces long
+// Segments of the eta / zeta sweeps.  A workgroup owns 64 lines and one
+// segment of S nodes, evaluating S+1 faces four at a time.  The plan
+// minimises (rounds of resident workgroups) x (iterations per workgroup),
+// with two resident workgroups per CU on 256 CUs.
 void plan_segments(const GeoK& G, int ndim, SweepArgs& a) {
-    const long target = 256L * 4 * 64 * 4;  // 4 waves per SIMD on 256 CUs
+    const long resident = 256L * 2;
     for (int d = 1; d < ndim; ++d) {
         const int oth = d == 1 ? 2 : 1;
-        const long lines = (long)G.n[0] * G.n[oth];
-        long nseg = (target + lines - 1) / lines;
-        const long maxseg = (G.n[d] + 7) / 8;
-        if (nseg > maxseg) nseg = maxseg;
-        if (nseg < 1) nseg = 1;
-        const int S = (int)((G.n[d] + nseg - 1) / nseg);
-        a.S[d] = S;
-        a.nseg[d] = (int)((G.n[d] + S - 1) / S);
+        const long lblocks = ((long)G.n[0] * G.n[oth] + 63) / 64;
+        const int nd = G.n[d];
+        long best = -1;
+        int bestS = nd;
+        for (int ns = 1; ns <= nd; ++ns) {
+            const int S = (nd + ns - 1) / ns;
+            if (S < 4 && ns > 1) break;
+            const long segs = (nd + S - 1) / S;
+            const long iters = (S + 1 + 3) / 4;
+            const long rounds = (lblocks * segs + resident - 1) / resident;
+            const long cost = rounds * iters;
+            if (best < 0 || cost < best) {
+                best = cost;
+                bestS = S;
+            }
+        }
+        a.S[d] = bestS;
+        a.nseg[d] = (nd + bestS - 1) / bestS;
     }
     a.S[0] = a.nseg[0] = 0;
     if (ndim == 2) a.S[2] = a.nseg[2] = 0;
@@ -176,14 +189,13 @@ EpiK epi(int mode, double* R) {
 }
 
 // one residual evaluation; the last sweep applies `last`
-hipError_t run_residual(const Ctx& c, const double* met, const double* qs, const double* qb,
-                        double* R, const EpiK& last, hipStream_t s) {
+hipError_t run_residual(const Ctx& c, const double* met, const double* qs, double* R,
+                        const EpiK& last, hipStream_t s) {
     SweepArgs a;
     a.G = c.G;
     a.sk = c.sk;
     a.met = met;
     a.qs = qs;
-    a.qb = qb;
     a.ep_first = epi(EPI_FIRST, R);
     a.ep_mid = epi(EPI_MID, R);
     a.ep_last = last;
@@ -191,11 +203,18 @@ hipError_t run_residual(const Ctx& c, const double* met, const double* qs, const
     return c.stage(a, s);
 }
 
-// one TVD RK3 step: q -> A -> B -> q, residual accumulator R
+// one TVD RK3 step: q -> A -> B -> q with residual accumulator R; the
+// frozen ghost layers of q are copied into A and B first
 hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, double dt, hipStream_t s) {
     double* A = work;
     double* B = work + c.state_elems;
     double* R = work + 2 * c.state_elems;
+    bool frozen = false;
+    for (int d = 0; d < c.grid.ndim; ++d) frozen = frozen || c.grid.bc[d] == FP_BC_FROZEN;
+    if (frozen) {
+        hipLaunchKernelGGL(k_frozen_ghosts, dim3((unsigned)((c.G.vol + 255) / 256)), dim3(256), 0, s,
+                           c.G, c.grid.ndim, c.grid.ndim + 2, (const double*)q, A, B);
+    }
     const double* metV = met + (size_t)(c.grid.ndim == 3 ? 9 : 4) * c.G.vol;
     const double* in[3] = {q, A, B};
     double* out[3] = {A, B, q};
@@ -211,7 +230,16 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
         e.dt = dt;
         e.a = ca[k];
         e.b = cb[k];
-        hipError_t err = run_residual(c, met, in[k], q, R, e, s);
+        SweepArgs a;
+        a.G = c.G;
+        a.sk = c.sk;
+        a.met = met;
+        a.qs = in[k];
+        a.ep_first = epi(EPI_FIRST, R);
+        a.ep_mid = epi(EPI_MID, R);
+        a.ep_last = e;
+        plan_segments(c.G, c.grid.ndim, a);
+        hipError_t err = c.stage(a, s);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
@@ -255,7 +283,10 @@ size_t fp_coord_bytes(const fp_grid* g, int32_t Y) {
     return sizeof(double) * tot;
 }
 
-size_t fp_work_bytes(const fp_grid* g) { return 3 * fp_state_bytes(g); }
+size_t fp_work_bytes(const fp_grid* g) {
+    if (check_grid(g)) return 0;
+    return 3 * fp_state_bytes(g);
+}
 
 const char* fp_last_error(void) { return g_err.c_str(); }
 
@@ -341,7 +372,7 @@ fp_status fp_residual(const fp_grid* g, const fp_scheme* sch, const double* met,
     EpiK last = epi(EPI_LAST_RES, dqdt);
     last.out = dqdt;
     last.metV = met + (size_t)(g->ndim == 3 ? 9 : 4) * c.G.vol;
-    hipError_t e = run_residual(c, met, q, q, dqdt, last, (hipStream_t)stream);
+    hipError_t e = run_residual(c, met, q, dqdt, last, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fp_residual launch");
     return FP_OK;
 }
@@ -362,7 +393,6 @@ fp_status fp_residual_dir(const fp_grid* g, const fp_scheme* sch, const double* 
     a.sk = c.sk;
     a.met = met;
     a.qs = q;
-    a.qb = q;
     plan_segments(c.G, g->ndim, a);
     hipError_t e = f(a, dir, epi(accumulate ? EPI_MID : EPI_FIRST, acc), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fp_residual_dir launch");

@@ -1,20 +1,18 @@
 // fp_device.hpp -- device-side arithmetic of the free-stream-preserving face
-// flux for gfx950 (CDNA4, wave64).  Included by fp_kernels.hip only.
+// flux for gfx950 (CDNA4, wave64).  Included by the kernel headers only.
 //
-// One face i+1/2 of one grid line is evaluated by one lane.  The stencil
-// (state, 1/J and the metric vector of the sweep direction at nodes i-3..i+4)
-// lives in registers; nothing of the per-face pipeline touches memory.
-//
-// Steps (Sec. 3 of the paper, with the readings listed in the design notes):
-//   1. cell-face 1/J, Q~ = Q/J and metrics by the central interpolation of the
-//      metric order Y; reference state Q* = Q~_f / (1/J)_f        [FP64]
-//   2. reference face flux F~*_f = F(Q*) s_f                      [FP64]
-//   3. reference-subtracted stencil values dQ~_m, dF~_m           [FP64]
-//   4. Roe average of nodes i, i+1; unit normal; eigenvectors      [T]
-//   5. local Lax-Friedrichs speed per field (stencil maximum)      [T]
-//   6. characteristic projection and splitting                     [T]
-//   7. WENO5-JS or linear-upwind reconstruction of both parts      [T]
-//   8. back-projection, then the reference flux is added back      [T, FP64 add]
+// One face i+1/2 of one grid line is evaluated by one lane.  The lane reads
+// the stencil nodes through a loader (slot r = 0..7 <-> node i-3+r) phase by
+// phase, so that only the values of the current phase are live in registers:
+//   A. cell-face 1/J, metrics and Q~ = Q/J by the central interpolation of
+//      the metric order Y; reference state Q* = Q~_f/(1/J)_f and reference
+//      face flux F~*_f = F(Q*) s_f                                    [FP64]
+//   B. Roe average of nodes i, i+1, unit normal, eigen-structure       [T]
+//   C. per stencil node m = i-2..i+3: reference-subtracted dQ~_m, dF~_m
+//      [FP64], local Lax-Friedrichs speeds, characteristic projections [T]
+//   D. WENO5-JS of both split parts of every field, or (linear upwind) the
+//      closed form central6(dF~) + (1/60) R Lambda L Delta^5(dQ~)      [T]
+//   E. back-projection and add-back of F~*_f                   [T, FP64 add]
 // T is double for the FP64 path and float for the mixed path.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -27,14 +25,6 @@ struct SchemeK {
     int reform;  // 1: reference state subtracted (the paper); 0: standard scheme
 };
 
-// Stencil slots r = 0..7 hold nodes i-3 .. i+4 of the face i+1/2.
-template <int DIM>
-struct Stencil {
-    double q[8][DIM + 2];
-    double V[8];
-    double s[8][DIM];
-};
-
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
@@ -42,10 +32,20 @@ struct Stencil {
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// 1/x from the hardware approximation refined by two Newton steps
+// (y <- y + y(1 - x y)); within a couple of ulps for normal x.
+__device__ __forceinline__ double drcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 template <typename T>
 __device__ __forceinline__ T rcp(T x);
 template <>
-__device__ __forceinline__ double rcp<double>(double x) { return 1.0 / x; }
+__device__ __forceinline__ double rcp<double>(double x) { return drcp(x); }
 template <>
 __device__ __forceinline__ float rcp<float>(float x) { return fast_rcp(x); }
 
@@ -56,18 +56,20 @@ __device__ __forceinline__ double vsqrt<double>(double x) { return sqrt(x); }
 template <>
 __device__ __forceinline__ float vsqrt<float>(float x) { return fast_sqrt(x); }
 
-// central face interpolation of order Y from stencil slots (node i in slot 3)
+// central face interpolation weights of order Y on slot r (node i in slot 3)
 template <int Y>
-__device__ __forceinline__ double face_interp(const double (&w)[8]) {
+__device__ __forceinline__ constexpr double iw(int r) {
     if constexpr (Y == 2) {
-        return (w[3] + w[4]) * 0.5;
+        return (r == 3 || r == 4) ? 0.5 : 0.0;
     } else if constexpr (Y == 4) {
-        return (7.0 * (w[3] + w[4]) - (w[2] + w[5])) * (1.0 / 12.0);
+        return (r == 3 || r == 4) ? 7.0 / 12.0 : ((r == 2 || r == 5) ? -1.0 / 12.0 : 0.0);
     } else if constexpr (Y == 6) {
-        return (37.0 * (w[3] + w[4]) - 8.0 * (w[2] + w[5]) + (w[1] + w[6])) * (1.0 / 60.0);
+        return (r == 3 || r == 4) ? 37.0 / 60.0
+             : ((r == 2 || r == 5) ? -8.0 / 60.0 : ((r == 1 || r == 6) ? 1.0 / 60.0 : 0.0));
     } else {
-        return (533.0 * (w[3] + w[4]) - 139.0 * (w[2] + w[5]) + 29.0 * (w[1] + w[6])
-                - 3.0 * (w[0] + w[7])) * (1.0 / 840.0);
+        return (r == 3 || r == 4) ? 533.0 / 840.0
+             : (r == 2 || r == 5) ? -139.0 / 840.0
+             : (r == 1 || r == 6) ? 29.0 / 840.0 : -3.0 / 840.0;
     }
 }
 
@@ -89,7 +91,7 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
     d1 *= d1;
     d2 *= d2;
     const double a0 = 0.1 * (d1 * d2), a1 = 0.6 * (d0 * d2), a2 = 0.3 * (d0 * d1);
-    return (a0 * q0 + a1 * q1 + a2 * q2) / (6.0 * (a0 + a1 + a2));
+    return (a0 * q0 + a1 * q1 + a2 * q2) * drcp(6.0 * (a0 + a1 + a2));
 }
 
 // FP32 form: reciprocal weights (no overflow of the products for large beta)
@@ -110,293 +112,372 @@ __device__ __forceinline__ float weno5(float a, float b, float c, float d, float
     return (a0 * q0 + a1 * q1 + a2 * q2) * fast_rcp(6.0f * (a0 + a1 + a2));
 }
 
-template <typename T>
-__device__ __forceinline__ T linup5(T a, T b, T c, T d, T e) {
-    return (T(2) * a - T(13) * b + T(47) * c + T(27) * d - T(3) * e) * (T(1) / T(60));
-}
-
-template <int RECON, typename T>
-__device__ __forceinline__ T recon5(T a, T b, T c, T d, T e, T eps) {
-    if constexpr (RECON == 1)
-        return linup5<T>(a, b, c, d, e);
-    else
-        return weno5(a, b, c, d, e, eps);
-}
-
 // ---------------------------------------------------------------------------
-// the face flux
+// phase A: cell-face reference state
 // ---------------------------------------------------------------------------
 
-template <int DIM, int RECON, int Y, typename T>
-__device__ __forceinline__ void face_flux(const Stencil<DIM>& st, const SchemeK& sk,
-                                          double (&Fo)[DIM + 2]) {
-    constexpr int NV = DIM + 2;
-    constexpr int E = NV - 1;
-    const double gam = sk.gamma, gm1 = sk.gamma - 1.0;
-
-    // (1) face reference state with the metric-order interpolation
-    double w[8];
-    const double Vf = face_interp<Y>(st.V);
+template <int DIM>
+struct FaceRef {
+    double Vf;
     double sf[DIM];
+    double Qs[DIM + 2];  // Q* (zero for the standard scheme)
+    double us[DIM];      // u*
+    double ps;           // p*
+    double Fts[DIM + 2]; // F(Q*) . s_f
+    double snorm;
+};
+
+template <int DIM, int Y, class LD>
+__device__ __forceinline__ void face_ref(const LD& ld, const SchemeK& sk, FaceRef<DIM>& R) {
+    constexpr int NV = DIM + 2, E = NV - 1;
+    constexpr int r0 = 4 - Y / 2, r1 = 4 + Y / 2;  // interpolation slots [r0, r1)
+    double Vf = 0.0, sf[DIM], Qt[NV];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
+    for (int c = 0; c < DIM; ++c) sf[c] = 0.0;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) w[r] = st.s[r][c];
-        sf[c] = face_interp<Y>(w);
+    for (int v = 0; v < NV; ++v) Qt[v] = 0.0;
+#pragma unroll
+    for (int r = r0; r < r1; ++r) {
+        double q[NV], V, s[DIM];
+        ld.slot(r, q, V, s);
+        const double w = iw<Y>(r);
+        Vf += w * V;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) sf[c] += w * s[c];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Qt[v] += w * (q[v] * V);
     }
-    double Qs[NV], us[DIM], ps = 0.0;
+    R.Vf = Vf;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Qs[v] = 0.0;
+    for (int c = 0; c < DIM; ++c) R.sf[c] = sf[c];
+    R.ps = 0.0;
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) us[c] = 0.0;
+    for (int v = 0; v < NV; ++v) R.Qs[v] = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) R.us[c] = 0.0;
     if (sk.reform) {
-        const double iVf = 1.0 / Vf;
+        const double iVf = drcp(Vf);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-#pragma unroll
-            for (int r = 0; r < 8; ++r) w[r] = st.q[r][v] * st.V[r];
-            Qs[v] = face_interp<Y>(w) * iVf;
-        }
-        const double irs = 1.0 / Qs[0];
+        for (int v = 0; v < NV; ++v) R.Qs[v] = Qt[v] * iVf;
+        const double irs = drcp(R.Qs[0]);
         double m2 = 0.0;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            us[c] = Qs[1 + c] * irs;
-            m2 += Qs[1 + c] * us[c];
+            R.us[c] = R.Qs[1 + c] * irs;
+            m2 += R.Qs[1 + c] * R.us[c];
         }
-        ps = gm1 * (Qs[E] - 0.5 * m2);
+        R.ps = (sk.gamma - 1.0) * (R.Qs[E] - 0.5 * m2);
     }
-    // (2) reference face flux F(Q*) . s_f
-    double Fts[NV];
+    double U = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        U += R.us[c] * sf[c];
+        s2 += sf[c] * sf[c];
+    }
+    R.Fts[0] = R.Qs[0] * U;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) R.Fts[1 + c] = R.Qs[1 + c] * U + R.ps * sf[c];
+    R.Fts[E] = (R.Qs[E] + R.ps) * U;
+    R.snorm = sqrt(s2);
+}
+
+// ---------------------------------------------------------------------------
+// phase B: Roe average and characteristic basis
+// ---------------------------------------------------------------------------
+
+template <int DIM, typename T>
+struct Eig {
+    T n[DIM], uh[DIM], t1[DIM], t2[3];
+    T un, Hh, ch, ic, b2, hq2, ut1, ut2, sigma;
+};
+
+template <int DIM, typename T, class LD>
+__device__ __forceinline__ void roe(const LD& ld, const SchemeK& sk, const FaceRef<DIM>& R,
+                                    Eig<DIM, T>& S) {
+    constexpr int NV = DIM + 2, E = NV - 1;
+    const double gm1 = sk.gamma - 1.0;
+    const double isn = drcp(R.snorm);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) S.n[c] = T(R.sf[c] * isn);
+    S.sigma = T(R.snorm * drcp(R.Vf));
+    double uL[DIM], uR[DIM], HL, HR, rL, rR;
     {
-        double U = 0.0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) U += us[c] * sf[c];
-        Fts[0] = Qs[0] * U;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) Fts[1 + c] = Qs[1 + c] * U + ps * sf[c];
-        Fts[E] = (Qs[E] + ps) * U;
-    }
-
-    // unit normal and eigenvalue scale sigma = |s_f| / (1/J)_f
-    double s2 = 0.0;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) s2 += sf[c] * sf[c];
-    const double snorm = sqrt(s2);
-    const double isn = 1.0 / snorm;
-    T n[DIM];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) n[c] = T(sf[c] * isn);
-    const T sigma = T(snorm / Vf);
-
-    // (3) reference-subtracted values at m = i-2..i+3 (slots 1..6), plus the
-    // node velocities/sound speeds for the LF speeds and the Roe states
-    T dQ[6][NV], dF[6][NV];
-    T mxm = T(0), mx0 = T(0), mxp = T(0);
-    double rhoL = 0, rhoR = 0, uL[DIM], uR[DIM], HL = 0, HR = 0;
-#pragma unroll
-    for (int r = 1; r <= 6; ++r) {
-        const double rho = st.q[r][0];
-        const double ir = 1.0 / rho;
-        double u[DIM], m2 = 0.0, U = 0.0, Us = 0.0;
+        double q[NV], V, s[DIM];
+        ld.slot(3, q, V, s);
+        const double ir = drcp(q[0]);
+        double m2 = 0.0;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            u[c] = st.q[r][1 + c] * ir;
-            m2 += st.q[r][1 + c] * u[c];
-            U += u[c] * st.s[r][c];
-            Us += us[c] * st.s[r][c];
+            uL[c] = q[1 + c] * ir;
+            m2 += q[1 + c] * uL[c];
         }
-        const double p = gm1 * (st.q[r][E] - 0.5 * m2);
-        const double dp = p - ps;
-        dF[r - 1][0] = T(rho * U - Qs[0] * Us);
-#pragma unroll
-        for (int c = 0; c < DIM; ++c)
-            dF[r - 1][1 + c] = T(st.q[r][1 + c] * U - Qs[1 + c] * Us + dp * st.s[r][c]);
-        dF[r - 1][E] = T((st.q[r][E] + p) * U - (Qs[E] + ps) * Us);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) dQ[r - 1][v] = T((st.q[r][v] - Qs[v]) * st.V[r]);
-        // LF speeds
-        T un = T(0);
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) un += n[c] * T(u[c]);
-        const T cs = vsqrt<T>(T(gam * p * ir));
-        mxm = fmax(mxm, fabs(un - cs));
-        mx0 = fmax(mx0, fabs(un));
-        mxp = fmax(mxp, fabs(un + cs));
-        if (r == 3) {
-            rhoL = rho;
-            HL = (st.q[r][E] + p) * ir;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) uL[c] = u[c];
-        }
-        if (r == 4) {
-            rhoR = rho;
-            HR = (st.q[r][E] + p) * ir;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) uR[c] = u[c];
-        }
+        HL = (q[E] + gm1 * (q[E] - 0.5 * m2)) * ir;
+        rL = q[0];
     }
-    const T lam0 = sigma * mxm, lamm = sigma * mx0, lamL = sigma * mxp;
-
-    // (4) Roe average and characteristic basis
-    const T wL = vsqrt<T>(T(rhoL)), wR = vsqrt<T>(T(rhoR));
-    const T iw = rcp<T>(wL + wR);
-    T uh[DIM];
+    {
+        double q[NV], V, s[DIM];
+        ld.slot(4, q, V, s);
+        const double ir = drcp(q[0]);
+        double m2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            uR[c] = q[1 + c] * ir;
+            m2 += q[1 + c] * uR[c];
+        }
+        HR = (q[E] + gm1 * (q[E] - 0.5 * m2)) * ir;
+        rR = q[0];
+    }
+    const T wL = vsqrt<T>(T(rL)), wR = vsqrt<T>(T(rR));
+    const T iwr = rcp<T>(wL + wR);
     T q2 = T(0), un = T(0);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        uh[c] = (wL * T(uL[c]) + wR * T(uR[c])) * iw;
-        q2 += uh[c] * uh[c];
-        un += uh[c] * n[c];
+        S.uh[c] = (wL * T(uL[c]) + wR * T(uR[c])) * iwr;
+        q2 += S.uh[c] * S.uh[c];
+        un += S.uh[c] * S.n[c];
     }
-    const T Hh = (wL * T(HL) + wR * T(HR)) * iw;
-    const T c2 = T(gm1) * (Hh - T(0.5) * q2);
-    const T ch = vsqrt<T>(c2);
-    const T ic = rcp<T>(ch);
-    const T b2 = T(gm1) * rcp<T>(c2);
-    const T hq2 = T(0.5) * q2;
-
-    // tangent basis of the shear fields
-    T t1[DIM], t2[3];
+    S.un = un;
+    S.Hh = (wL * T(HL) + wR * T(HR)) * iwr;
+    const T c2 = T(gm1) * (S.Hh - T(0.5) * q2);
+    S.ch = vsqrt<T>(c2);
+    S.ic = rcp<T>(S.ch);
+    S.b2 = T(gm1) * rcp<T>(c2);
+    S.hq2 = T(0.5) * q2;
     if constexpr (DIM == 2) {
-        t1[0] = -n[1];
-        t1[1] = n[0];
+        S.t1[0] = -S.n[1];
+        S.t1[1] = S.n[0];
+        S.ut1 = S.uh[0] * S.t1[0] + S.uh[1] * S.t1[1];
+        S.ut2 = T(0);
     } else {
         // a = argmin |n_k|, components within 1e-10 count as tied and the
-        // lowest k wins; t1 = normalize(n x e_a)
+        // lowest k wins; t1 = normalize(n x e_a), t2 = n x t1
         const T tie = T(1e-10);
-        const T a0 = fabs(n[0]), a1 = fabs(n[1]), a2 = fabs(n[2]);
+        const T a0 = fabs(S.n[0]), a1 = fabs(S.n[1]), a2 = fabs(S.n[2]);
         int a = 0;
         T am = a0;
         if (a1 < am - tie) { a = 1; am = a1; }
         if (a2 < am - tie) { a = 2; }
         T x0, x1, x2;
-        if (a == 0) { x0 = T(0); x1 = n[2]; x2 = -n[1]; }
-        else if (a == 1) { x0 = -n[2]; x1 = T(0); x2 = n[0]; }
-        else { x0 = n[1]; x1 = -n[0]; x2 = T(0); }
+        if (a == 0) { x0 = T(0); x1 = S.n[2]; x2 = -S.n[1]; }
+        else if (a == 1) { x0 = -S.n[2]; x1 = T(0); x2 = S.n[0]; }
+        else { x0 = S.n[1]; x1 = -S.n[0]; x2 = T(0); }
         const T ix = rcp<T>(vsqrt<T>(x0 * x0 + x1 * x1 + x2 * x2));
-        t1[0] = x0 * ix;
-        t1[1] = x1 * ix;
-        t1[2] = x2 * ix;
-        t2[0] = n[1] * t1[2] - n[2] * t1[1];
-        t2[1] = n[2] * t1[0] - n[0] * t1[2];
-        t2[2] = n[0] * t1[1] - n[1] * t1[0];
+        S.t1[0] = x0 * ix;
+        S.t1[1] = x1 * ix;
+        S.t1[2] = x2 * ix;
+        S.t2[0] = S.n[1] * S.t1[2] - S.n[2] * S.t1[1];
+        S.t2[1] = S.n[2] * S.t1[0] - S.n[0] * S.t1[2];
+        S.t2[2] = S.n[0] * S.t1[1] - S.n[1] * S.t1[0];
+        S.ut1 = S.uh[0] * S.t1[0] + S.uh[1] * S.t1[1] + S.uh[2] * S.t1[2];
+        S.ut2 = S.uh[0] * S.t2[0] + S.uh[1] * S.t2[1] + S.uh[2] * S.t2[2];
     }
-    T ut1 = T(0), ut2 = T(0);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) ut1 += uh[c] * t1[c];
-    if constexpr (DIM == 3) ut2 = uh[0] * t2[0] + uh[1] * t2[1] + uh[2] * t2[2];
+}
 
-    // (5)-(7): per characteristic field, project, split, reconstruct
-    const T eps = T(sk.eps);
-    T hs[NV];
-    // acoustic and entropy fields share phi/psi: l_0 w = (phi - psi)/2,
-    // l_1 w = w_0 - phi, l_E w = (phi + psi)/2 with
-    // phi = b2 (|u|^2/2 w_0 - u.w_m + w_E), psi = (n.w_m - u_n w_0)/c
-    T pF[6], sF[6], pQ[6], sQ[6];
-#pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        T uw = T(0), nw = T(0), uq = T(0), nq = T(0);
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            uw += uh[c] * dF[r][1 + c];
-            nw += n[c] * dF[r][1 + c];
-            uq += uh[c] * dQ[r][1 + c];
-            nq += n[c] * dQ[r][1 + c];
-        }
-        pF[r] = b2 * (hq2 * dF[r][0] - uw + dF[r][E]);
-        sF[r] = (nw - un * dF[r][0]) * ic;
-        pQ[r] = b2 * (hq2 * dQ[r][0] - uq + dQ[r][E]);
-        sQ[r] = (nq - un * dQ[r][0]) * ic;
-    }
-    {
-        // field 0 (u_n - c)
-        T vp[6], vm[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            const T a = T(0.5) * (pF[r] - sF[r]);
-            const T b = T(0.5) * (pQ[r] - sQ[r]);
-            vp[r] = T(0.5) * (a + lam0 * b);
-            vm[r] = T(0.5) * (a - lam0 * b);
-        }
-        hs[0] = recon5<RECON, T>(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
-                recon5<RECON, T>(vm[5], vm[4], vm[3], vm[2], vm[1], eps);
-    }
-    {
-        // field E (u_n + c)
-        T vp[6], vm[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            const T a = T(0.5) * (pF[r] + sF[r]);
-            const T b = T(0.5) * (pQ[r] + sQ[r]);
-            vp[r] = T(0.5) * (a + lamL * b);
-            vm[r] = T(0.5) * (a - lamL * b);
-        }
-        hs[E] = recon5<RECON, T>(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
-                recon5<RECON, T>(vm[5], vm[4], vm[3], vm[2], vm[1], eps);
-    }
-    {
-        // field 1 (entropy, u_n)
-        T vp[6], vm[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            const T a = dF[r][0] - pF[r];
-            const T b = dQ[r][0] - pQ[r];
-            vp[r] = T(0.5) * (a + lamm * b);
-            vm[r] = T(0.5) * (a - lamm * b);
-        }
-        hs[1] = recon5<RECON, T>(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
-                recon5<RECON, T>(vm[5], vm[4], vm[3], vm[2], vm[1], eps);
-    }
-    {
-        // shear field along t1: l = (-u.t1, t1, 0)
-        T vp[6], vm[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            T a = -ut1 * dF[r][0], b = -ut1 * dQ[r][0];
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                a += t1[c] * dF[r][1 + c];
-                b += t1[c] * dQ[r][1 + c];
-            }
-            vp[r] = T(0.5) * (a + lamm * b);
-            vm[r] = T(0.5) * (a - lamm * b);
-        }
-        hs[2] = recon5<RECON, T>(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
-                recon5<RECON, T>(vm[5], vm[4], vm[3], vm[2], vm[1], eps);
-    }
-    if constexpr (DIM == 3) {
-        T vp[6], vm[6];
-#pragma unroll
-        for (int r = 0; r < 6; ++r) {
-            T a = -ut2 * dF[r][0], b = -ut2 * dQ[r][0];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                a += t2[c] * dF[r][1 + c];
-                b += t2[c] * dQ[r][1 + c];
-            }
-            vp[r] = T(0.5) * (a + lamm * b);
-            vm[r] = T(0.5) * (a - lamm * b);
-        }
-        hs[3] = recon5<RECON, T>(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
-                recon5<RECON, T>(vm[5], vm[4], vm[3], vm[2], vm[1], eps);
-    }
+// ---------------------------------------------------------------------------
+// phase C helper: reference-subtracted values and LF speeds at one node
+// ---------------------------------------------------------------------------
 
-    // (8) back-projection R h and add-back of the reference flux
-    const T h0 = hs[0], h1 = hs[1], hE = hs[E];
-    const T hsum = h0 + h1 + hE, hdif = hE - h0;
-    Fo[0] = Fts[0] + double(hsum);
+template <int DIM, typename T>
+struct NodeDiff {
+    double dQ[DIM + 2], dF[DIM + 2];
+    T un, cs;
+};
+
+template <int DIM, typename T, class LD>
+__device__ __forceinline__ void node_diff(const LD& ld, int r, const SchemeK& sk,
+                                          const FaceRef<DIM>& R, const Eig<DIM, T>& S,
+                                          NodeDiff<DIM, T>& N) {
+    constexpr int NV = DIM + 2, E = NV - 1;
+    const double gm1 = sk.gamma - 1.0;
+    double q[NV], V, s[DIM];
+    ld.slot(r, q, V, s);
+    const double ir = drcp(q[0]);
+    double u[DIM], m2 = 0.0, U = 0.0, Us = 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        T m = uh[c] * hsum + ch * n[c] * hdif + t1[c] * hs[2];
-        if constexpr (DIM == 3) m += t2[c] * hs[3];
-        Fo[1 + c] = Fts[1 + c] + double(m);
+        u[c] = q[1 + c] * ir;
+        m2 += q[1 + c] * u[c];
+        U += u[c] * s[c];
+        Us += R.us[c] * s[c];
     }
-    {
-        T en = Hh * (h0 + hE) + ch * un * hdif + hq2 * h1 + ut1 * hs[2];
-        if constexpr (DIM == 3) en += ut2 * hs[3];
-        Fo[E] = Fts[E] + double(en);
+    const double p = gm1 * (q[E] - 0.5 * m2);
+    const double dp = p - R.ps;
+    N.dF[0] = q[0] * U - R.Qs[0] * Us;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) N.dF[1 + c] = q[1 + c] * U - R.Qs[1 + c] * Us + dp * s[c];
+    N.dF[E] = (q[E] + p) * U - (R.Qs[E] + R.ps) * Us;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) N.dQ[v] = (q[v] - R.Qs[v]) * V;
+    T un = T(0);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) un += S.n[c] * T(u[c]);
+    N.un = un;
+    N.cs = vsqrt<T>(T(sk.gamma * p * ir));
+}
+
+// l_s . w for the five (four in 2D) fields, using the structure of the Euler
+// eigenvectors: l_0 w = (phi - psi)/2, l_1 w = w_0 - phi, l_t w = t.w_m -
+// (u.t) w_0, l_E w = (phi + psi)/2 with phi = b2 (|u|^2/2 w_0 - u.w_m + w_E)
+// and psi = (n.w_m - u_n w_0)/c.
+template <int DIM, typename T>
+__device__ __forceinline__ void project(const Eig<DIM, T>& S, const T (&w)[DIM + 2],
+                                        T (&a)[DIM + 2]) {
+    constexpr int E = DIM + 1;
+    T uw = T(0), nw = T(0), t1w = T(0), t2w = T(0);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        uw += S.uh[c] * w[1 + c];
+        nw += S.n[c] * w[1 + c];
+        t1w += S.t1[c] * w[1 + c];
+        if constexpr (DIM == 3) t2w += S.t2[c] * w[1 + c];
     }
+    const T phi = S.b2 * (S.hq2 * w[0] - uw + w[E]);
+    const T psi = (nw - S.un * w[0]) * S.ic;
+    a[0] = T(0.5) * (phi - psi);
+    a[1] = w[0] - phi;
+    a[2] = t1w - S.ut1 * w[0];
+    if constexpr (DIM == 3) a[3] = t2w - S.ut2 * w[0];
+    a[E] = T(0.5) * (phi + psi);
+}
+
+// R h: back to conservative components
+template <int DIM, typename T>
+__device__ __forceinline__ void backproject(const Eig<DIM, T>& S, const T (&h)[DIM + 2],
+                                            T (&o)[DIM + 2]) {
+    constexpr int E = DIM + 1;
+    const T h0 = h[0], h1 = h[1], hE = h[E];
+    const T hsum = h0 + h1 + hE, hdif = hE - h0;
+    o[0] = hsum;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        T m = S.uh[c] * hsum + S.ch * S.n[c] * hdif + S.t1[c] * h[2];
+        if constexpr (DIM == 3) m += S.t2[c] * h[3];
+        o[1 + c] = m;
+    }
+    T en = S.Hh * (h0 + hE) + S.ch * S.un * hdif + S.hq2 * h1 + S.ut1 * h[2];
+    if constexpr (DIM == 3) en += S.ut2 * h[3];
+    o[E] = en;
+}
+
+// ---------------------------------------------------------------------------
+// the face flux: WENO5-JS
+// ---------------------------------------------------------------------------
+
+template <int DIM, int Y, typename T, class LD>
+__device__ __forceinline__ void face_flux_weno(const LD& ld, const SchemeK& sk,
+                                               double (&Fo)[DIM + 2]) {
+    constexpr int NV = DIM + 2, E = NV - 1;
+    FaceRef<DIM> R;
+    face_ref<DIM, Y>(ld, sk, R);
+    Eig<DIM, T> S;
+    roe<DIM, T>(ld.after(R.Vf), sk, R, S);
+    // per stencil node: projections of dF~ (a) and dQ~ (b) on every field
+    T a[NV][6], b[NV][6];
+    T mxm = T(0), mx0 = T(0), mxp = T(0);
+    double chain = double(S.ic);
+#pragma unroll
+    for (int r = 1; r <= 6; ++r) {
+        NodeDiff<DIM, T> N;
+        node_diff<DIM, T>(ld.after(chain), r, sk, R, S, N);
+        chain = N.dQ[0];
+        mxm = fmax(mxm, fabs(N.un - N.cs));
+        mx0 = fmax(mx0, fabs(N.un));
+        mxp = fmax(mxp, fabs(N.un + N.cs));
+        T w[NV], pa[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = T(N.dF[v]);
+        project<DIM, T>(S, w, pa);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a[v][r - 1] = pa[v];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = T(N.dQ[v]);
+        project<DIM, T>(S, w, pa);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) b[v][r - 1] = pa[v];
+    }
+    // local LF speeds: fields (u_n - c), (u_n) x (DIM - 1 + 1), (u_n + c)
+    T lam[NV];
+    lam[0] = S.sigma * mxm;
+#pragma unroll
+    for (int v = 1; v < E; ++v) lam[v] = S.sigma * mx0;
+    lam[E] = S.sigma * mxp;
+    const T eps = T(sk.eps);
+    T h[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T vp[6], vm[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            vp[r] = T(0.5) * (a[v][r] + lam[v] * b[v][r]);
+            vm[r] = T(0.5) * (a[v][r] - lam[v] * b[v][r]);
+        }
+        h[v] = weno5(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
+               weno5(vm[5], vm[4], vm[3], vm[2], vm[1], eps);
+    }
+    T o[NV];
+    backproject<DIM, T>(S, h, o);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fo[v] = R.Fts[v] + double(o[v]);
+}
+
+// ---------------------------------------------------------------------------
+// the face flux: fifth-order linear upwind
+// ---------------------------------------------------------------------------
+// With the optimal weights the two split parts reconstruct linearly, and
+// since (LU5+ + LU5-)/2 is the sixth-order central interpolation and
+// (LU5+ - LU5-)/2 the fifth difference (1,-5,10,-10,5,-1)/60,
+//   sum_s r_s (h+_s + h-_s) = central6(dF~) + (1/60) R Lambda L Delta^5(dQ~),
+// which is the linear-upwind member of eq. new_form_linear_upwind.
+
+template <int DIM, int Y, typename T, class LD>
+__device__ __forceinline__ void face_flux_lu5(const LD& ld, const SchemeK& sk,
+                                              double (&Fo)[DIM + 2]) {
+    constexpr int NV = DIM + 2, E = NV - 1;
+    constexpr double c6[6] = {1.0 / 60, -8.0 / 60, 37.0 / 60, 37.0 / 60, -8.0 / 60, 1.0 / 60};
+    constexpr double d5[6] = {1.0, -5.0, 10.0, -10.0, 5.0, -1.0};
+    FaceRef<DIM> R;
+    face_ref<DIM, Y>(ld, sk, R);
+    Eig<DIM, T> S;
+    roe<DIM, T>(ld.after(R.Vf), sk, R, S);
+    double cen[NV], del[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cen[v] = del[v] = 0.0;
+    T mxm = T(0), mx0 = T(0), mxp = T(0);
+    double chain = double(S.ic);
+#pragma unroll
+    for (int r = 1; r <= 6; ++r) {
+        NodeDiff<DIM, T> N;
+        node_diff<DIM, T>(ld.after(chain), r, sk, R, S, N);
+        chain = N.dQ[0];
+        mxm = fmax(mxm, fabs(N.un - N.cs));
+        mx0 = fmax(mx0, fabs(N.un));
+        mxp = fmax(mxp, fabs(N.un + N.cs));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            cen[v] += c6[r - 1] * N.dF[v];
+            del[v] += d5[r - 1] * N.dQ[v];
+        }
+    }
+    T w[NV], pa[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = T(del[v]);
+    project<DIM, T>(S, w, pa);
+    pa[0] *= S.sigma * mxm;
+#pragma unroll
+    for (int v = 1; v < E; ++v) pa[v] *= S.sigma * mx0;
+    pa[E] *= S.sigma * mxp;
+    T o[NV];
+    backproject<DIM, T>(S, pa, o);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fo[v] = R.Fts[v] + cen[v] + double(o[v]) * (1.0 / 60.0);
+}
+
+template <int DIM, int RECON, int Y, typename T, class LD>
+__device__ __forceinline__ void face_flux(const LD& ld, const SchemeK& sk, double (&Fo)[DIM + 2]) {
+    if constexpr (RECON == 1)
+        face_flux_lu5<DIM, Y, T>(ld, sk, Fo);
+    else
+        face_flux_weno<DIM, Y, T>(ld, sk, Fo);
 }
 
 }  // namespace fpk

@@ -24,24 +24,29 @@ inline unsigned blocks_for(long threads, int per_block) {
 }
 
 template <int DIM, int DIR, int Y>
-void launch_march(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
+void launch_wg(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
     constexpr int OTH = DIR == 1 ? 2 : 1;
-    const long threads = (long)a.G.n[0] * a.G.n[OTH] * a.nseg[DIR];
-    hipLaunchKernelGGL((k_sweep_march<DIM, DIR, R, Y, P>), dim3(blocks_for(threads, 256)), dim3(256),
-                       0, s, a.G, a.sk, a.met, a.qs, a.qb, ep, a.S[DIR], a.nseg[DIR]);
+    const long lblocks = ((long)a.G.n[0] * a.G.n[OTH] + 63) / 64;
+    hipLaunchKernelGGL((k_sweep_wg<DIM, DIR, R, Y, P>), dim3((unsigned)(lblocks * a.nseg[DIR])),
+                       dim3(256), 0, s, a.G, a.sk, a.met, a.qs, ep, a.S[DIR], a.nseg[DIR]);
+}
+
+template <int DIM, int Y>
+void launch_x(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
+    const long faces = (long)(a.G.n[0] + 1) * a.G.n[1] * a.G.n[2];
+    const long waves = (faces + 62) / 63;
+    hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, a.G,
+                       a.sk, a.met, a.qs, ep);
 }
 
 template <int DIM, int Y>
 hipError_t run_stage(const SweepArgs& a, hipStream_t s) {
-    const long faces = (long)(a.G.n[0] + 1) * a.G.n[1] * a.G.n[2];
-    const long waves = (faces + 62) / 63;
-    hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, a.G,
-                       a.sk, a.met, a.qs, a.qb, a.ep_first);
+    launch_x<DIM, Y>(a, a.ep_first, s);
     if constexpr (DIM == 3) {
-        launch_march<3, 1, Y>(a, a.ep_mid, s);
-        launch_march<3, 2, Y>(a, a.ep_last, s);
+        launch_wg<3, 1, Y>(a, a.ep_mid, s);
+        launch_wg<3, 2, Y>(a, a.ep_last, s);
     } else {
-        launch_march<2, 1, Y>(a, a.ep_last, s);
+        launch_wg<2, 1, Y>(a, a.ep_last, s);
     }
     return hipGetLastError();
 }
@@ -49,14 +54,11 @@ hipError_t run_stage(const SweepArgs& a, hipStream_t s) {
 template <int DIM, int Y>
 hipError_t run_dir(const SweepArgs& a, int dir, const EpiK& ep, hipStream_t s) {
     if (dir == 0) {
-        const long faces = (long)(a.G.n[0] + 1) * a.G.n[1] * a.G.n[2];
-        const long waves = (faces + 62) / 63;
-        hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3(blocks_for(waves, 4)), dim3(256), 0, s,
-                           a.G, a.sk, a.met, a.qs, a.qb, ep);
+        launch_x<DIM, Y>(a, ep, s);
     } else if (dir == 1) {
-        launch_march<DIM, 1, Y>(a, ep, s);
+        launch_wg<DIM, 1, Y>(a, ep, s);
     } else if constexpr (DIM == 3) {
-        launch_march<3, 2, Y>(a, ep, s);
+        launch_wg<3, 2, Y>(a, ep, s);
     }
     return hipGetLastError();
 }

@@ -8,6 +8,13 @@
 
 #include "fp_device.hpp"
 
+// Occupancy target of the face kernels: two waves per SIMD fits the FP64
+// WENO face (the 6-node x 5-field characteristic values dominate) without
+// spilling.
+#ifndef FP_SWEEP_ATTR
+#define FP_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(2, 2)))
+#endif
+
 namespace fpk {
 
 // Geometry of one structured block as the kernels see it.  Offsets are in
@@ -65,50 +72,60 @@ __device__ __forceinline__ void epilogue(const EpiK& ep, long vol, long off, con
     }
 }
 
-// Load the stencil of face i+1/2 of the line starting at offset lb (node 0 of
-// the line) along axis DIR.  State values outside the interior come from the
-// periodic image of qs or, on a frozen axis, from the ghost layers of qb.
-// Metrics are read directly (their ghost layers are filled by fp_metrics).
-template <int DIM, int DIR, int Y>
-__device__ __forceinline__ void load_stencil(const GeoK& G, const double* __restrict__ met,
-                                             const double* qs, const double* qb, long lb, int i,
-                                             Stencil<DIM>& st) {
-    constexpr int NV = DIM + 2;
-    constexpr int NMET = DIM == 3 ? 10 : 5;
-    constexpr int r0 = Y == 8 ? 0 : 1;
-    constexpr int r1 = Y == 8 ? 8 : 7;
-    const long sd = G.sd[DIR];
-    const int nd = G.n[DIR];
-    const bool per = G.bc[DIR] == 0;
-#pragma unroll
-    for (int r = r0; r < r1; ++r) {
+// Load at a 32-bit byte offset from a wave-uniform base: the base pointers
+// (array + variable * vol) are computed in scalar registers and every lane
+// adds one 32-bit offset, so no 64-bit vector address arithmetic is spent per
+// load.  A variable array must stay below 4 GiB (checked by the host).
+__device__ __forceinline__ double ldg(const double* base, unsigned byteoff) {
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byteoff);
+}
+
+// Reads the stencil of face i+1/2 of one grid line along axis DIR: slot r
+// holds node i-3+r.  Periodic axes wrap to the image inside the interior;
+// frozen axes read the ghost layers of the same array (the RK3 driver copies
+// the caller's frozen ghost values into its stage arrays).  Metrics are read
+// directly: fp_metrics fills their ghost layers.
+template <int DIM, int DIR>
+struct LineLoader {
+    const double* __restrict__ met;
+    const double* q;
+    long vol;       // elements per variable
+    unsigned lb;    // element offset of node 0 of the line
+    int sd;         // element stride along the line
+    int i;          // the face is i+1/2
+    int nd;         // interior nodes along the line
+    int per;        // periodic axis
+
+    __device__ __forceinline__ LineLoader(const GeoK& G, const double* met_, const double* q_,
+                                          long lb_, int i_)
+        : met(met_), q(q_), vol(G.vol), lb((unsigned)lb_), sd((int)G.sd[DIR]), i(i_),
+          nd(G.n[DIR]), per(G.bc[DIR] == 0) {}
+
+    // A copy whose loads cannot be hoisted above, or merged with loads
+    // before, the computation of `dep`: the line offset passes through an
+    // empty asm that takes `dep` as input.  This bounds the live range of the
+    // stencil values to one phase of the face computation.
+    __device__ __forceinline__ LineLoader after(double dep) const {
+        LineLoader c = *this;
+        asm volatile("" : "+v"(c.lb) : "v"(dep));
+        return c;
+    }
+
+    __device__ __forceinline__ void slot(int r, double (&qv)[DIM + 2], double& V,
+                                         double (&s)[DIM]) const {
+        constexpr int NMET = DIM == 3 ? 10 : 5;
         const int t = i - 3 + r;
         int tt = t;
-        const double* src = qs;
-        if (t < 0 || t >= nd) {
-            if (per)
-                tt = t < 0 ? t + nd : t - nd;
-            else
-                src = qb;
-        }
-        const long off = lb + (long)tt * sd;
+        if (per) tt = t < 0 ? t + nd : (t >= nd ? t - nd : t);
+        const unsigned off = (lb + (unsigned)(tt * sd)) * 8u;
+        const unsigned moff = (lb + (unsigned)(t * sd)) * 8u;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) st.q[r][v] = src[v * G.vol + off];
-        const long moff = lb + (long)t * sd;
-        st.V[r] = met[(NMET - 1) * G.vol + moff];
+        for (int v = 0; v < DIM + 2; ++v) qv[v] = ldg(q + v * vol, off);
+        V = ldg(met + (NMET - 1) * vol, moff);
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) st.s[r][c] = met[(DIR * DIM + c) * G.vol + moff];
+        for (int c = 0; c < DIM; ++c) s[c] = ldg(met + (DIR * DIM + c) * vol, moff);
     }
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        if (r >= r0 && r < r1) continue;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) st.q[r][v] = 0.0;
-        st.V[r] = 0.0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) st.s[r][c] = 0.0;
-    }
-}
+};
 
 template <int PREC>
 using char_t = typename std::conditional<PREC == 1, float, double>::type;
@@ -118,8 +135,9 @@ using char_t = typename std::conditional<PREC == 1, float, double>::type;
 // so that every lane but the first takes its left neighbour's flux by a lane
 // shift and forms the flux difference of its node.
 template <int DIM, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) void k_sweep_x(GeoK G, SchemeK sk, const double* __restrict__ met,
-                                                  const double* qs, const double* qb, EpiK ep) {
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK sk,
+                                                               const double* __restrict__ met,
+                                                               const double* qs, EpiK ep) {
     constexpr int NV = DIM + 2;
     const int lane = threadIdx.x & 63;
     const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -138,9 +156,8 @@ __global__ __launch_bounds__(256) void k_sweep_x(GeoK G, SchemeK sk, const doubl
         const int j = (int)(line % G.n[1]);
         const int k = (int)(line / G.n[1]);
         lb = G.base + (long)j * G.sd[1] + (long)k * G.sd[2];
-        Stencil<DIM> st;
-        load_stencil<DIM, 0, Y>(G, met, qs, qb, lb, f - 1, st);
-        face_flux<DIM, RECON, Y, char_t<PREC>>(st, sk, fl);
+        const LineLoader<DIM, 0> ld(G, met, qs, lb, f - 1);
+        face_flux<DIM, RECON, Y, char_t<PREC>>(ld, sk, fl);
     }
     double d[NV];
 #pragma unroll
@@ -148,51 +165,67 @@ __global__ __launch_bounds__(256) void k_sweep_x(GeoK G, SchemeK sk, const doubl
     if (active && lane > 0 && f > 0) epilogue<NV>(ep, G.vol, lb + (f - 1), d);
 }
 
-// eta / zeta sweeps: one lane per line segment, lanes along i (coalesced);
-// each lane marches along the sweep axis and carries the previous face flux.
+// eta / zeta sweeps: a workgroup of four waves owns 64 grid lines along DIR
+// (consecutive in the flattened (i, other) index, so loads are coalesced)
+// and one segment [k0, k1) of them.  Per iteration wave w evaluates the face
+// f+1/2, f = k0 - 1 + 4 it + w, on its 64 lines; the fluxes go to LDS (three
+// rotating buffers of four rows, so one barrier per iteration suffices) and
+// wave w then forms node f's difference F'_{f+1/2} - F'_{f-1/2}.  Every
+// thread runs the same number of iterations (no early exit before a barrier).
 template <int DIM, int DIR, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) void k_sweep_march(GeoK G, SchemeK sk,
-                                                      const double* __restrict__ met,
-                                                      const double* qs, const double* qb, EpiK ep,
-                                                      int S, int nseg) {
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK sk,
+                                                                const double* __restrict__ met,
+                                                                const double* qs, EpiK ep, int S,
+                                                                int nseg) {
     constexpr int NV = DIM + 2;
     constexpr int OTH = DIR == 1 ? 2 : 1;
-    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int n0 = G.n[0];
-    const int no = G.n[OTH];
-    if (tid >= (long)n0 * no * nseg) return;
-    const int i = (int)(tid % n0);
-    const long rest = tid / n0;
-    const int o = (int)(rest % no);
-    const int seg = (int)(rest / no);
-    const int nd = G.n[DIR];
-    const int t0 = seg * S;
-    const int t1 = min(t0 + S, nd);
-    if (t0 >= t1) return;
+    __shared__ double fl[3][4][NV][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const long nlines = (long)G.n[0] * G.n[OTH];
+    const long lblocks = (nlines + 63) / 64;
+    const long blk = blockIdx.x;
+    const long lineblk = blk % lblocks;
+    const int seg = (int)(blk / lblocks);
+    const long line = lineblk * 64 + lane;
+    const bool lane_ok = line < nlines;
+    const int i = lane_ok ? (int)(line % G.n[0]) : 0;
+    const int o = lane_ok ? (int)(line / G.n[0]) : 0;
     const long lb = G.base + i + (long)o * G.sd[OTH];
-    double Fp[NV];
+    const int nd = G.n[DIR];
+    const int k0 = seg * S;
+    const int k1 = min(k0 + S, nd);
+    const int iters = (k1 - k0 + 1 + 3) / 4;  // faces k0-1/2 .. k1-1/2
+    for (int it = 0; it < iters; ++it) {
+        const int f = k0 - 1 + 4 * it + w;
+        const int buf = it % 3;
+        double F[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fp[v] = 0.0;
-    for (int t = t0 - 1; t < t1; ++t) {
-        Stencil<DIM> st;
-        load_stencil<DIM, DIR, Y>(G, met, qs, qb, lb, t, st);
-        double Fc[NV];
-        face_flux<DIM, RECON, Y, char_t<PREC>>(st, sk, Fc);
-        if (t >= t0) {
-            double d[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) d[v] = Fc[v] - Fp[v];
-            epilogue<NV>(ep, G.vol, lb + (long)t * G.sd[DIR], d);
+        for (int v = 0; v < NV; ++v) F[v] = 0.0;
+        if (lane_ok && f < k1) {
+            const LineLoader<DIM, DIR> ld(G, met, qs, lb, f);
+            face_flux<DIM, RECON, Y, char_t<PREC>>(ld, sk, F);
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fp[v] = Fc[v];
+        for (int v = 0; v < NV; ++v) fl[buf][w][v][lane] = F[v];
+        __syncthreads();
+        if (lane_ok && f >= k0 && f < k1) {
+            const int pb = w > 0 ? buf : (it + 2) % 3;
+            const int pr = w > 0 ? w - 1 : 3;
+            double d[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) d[v] = F[v] - fl[pb][pr][v][lane];
+            epilogue<NV>(ep, G.vol, lb + (long)f * G.sd[DIR], d);
+        }
     }
 }
 
-// Every face of direction DIR, one lane per face (parity checks).
+// Every face of direction DIR, one lane per face, lanes along i (coalesced):
+// the face fluxes of fp_face_fluxes.
 template <int DIM, int DIR, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) void k_face_flux(GeoK G, SchemeK sk, const double* __restrict__ met,
-                                                    const double* q, double* out) {
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_face_flux(GeoK G, SchemeK sk,
+                                                                 const double* __restrict__ met,
+                                                                 const double* qs, double* out) {
     constexpr int NV = DIM + 2;
     int ext[3] = {G.n[0], G.n[1], G.n[2]};
     ext[DIR] += 1;
@@ -207,10 +240,9 @@ __global__ __launch_bounds__(256) void k_face_flux(GeoK G, SchemeK sk, const dou
 #pragma unroll
     for (int d = 0; d < 3; ++d)
         if (d != DIR) lb += (long)c[d] * G.sd[d];
-    Stencil<DIM> st;
-    load_stencil<DIM, DIR, Y>(G, met, q, q, lb, c[DIR] - 1, st);
+    const LineLoader<DIM, DIR> ld(G, met, qs, lb, c[DIR] - 1);
     double fl[NV];
-    face_flux<DIM, RECON, Y, char_t<PREC>>(st, sk, fl);
+    face_flux<DIM, RECON, Y, char_t<PREC>>(ld, sk, fl);
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v * total + tid] = fl[v];
 }
@@ -224,7 +256,6 @@ struct SweepArgs {
     SchemeK sk;
     const double* met;
     const double* qs;
-    const double* qb;
     EpiK ep_first, ep_mid, ep_last;
     int S[3];
     int nseg[3];

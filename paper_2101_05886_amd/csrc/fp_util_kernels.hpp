@@ -138,6 +138,39 @@ __global__ __launch_bounds__(256) void k_periodic_fill(GeoK G, int ndim, int nva
     for (int v = 0; v < nvar; ++v) a[v * G.vol + tid] = a[v * G.vol + src];
 }
 
+// Copies the ghost layers of the frozen axes (nodes outside the interior
+// along a frozen axis, interior along the others: the only ghost nodes the
+// sweeps read) of src into dst1 and dst2.  The RK3 driver uses it to give
+// its stage arrays the caller's boundary values.
+__global__ __launch_bounds__(256) void k_frozen_ghosts(GeoK G, int ndim, int nvar,
+                                                       const double* __restrict__ src,
+                                                       double* __restrict__ dst1,
+                                                       double* __restrict__ dst2) {
+    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= G.vol) return;
+    int N[3];
+    N[0] = G.n[0] + 2 * G.g;
+    N[1] = G.n[1] + 2 * G.g;
+    N[2] = ndim == 3 ? G.n[2] + 2 * G.g : 1;
+    int p[3];
+    p[0] = (int)(tid % N[0]) - G.g;
+    p[1] = (int)((tid / N[0]) % N[1]) - G.g;
+    p[2] = ndim == 3 ? (int)(tid / ((long)N[0] * N[1])) - G.g : 0;
+    int outside = 0, frozen_out = 0;
+    for (int d = 0; d < ndim; ++d) {
+        if (p[d] < 0 || p[d] >= G.n[d]) {
+            ++outside;
+            if (G.bc[d] != 0) frozen_out = 1;
+        }
+    }
+    if (outside != 1 || !frozen_out) return;
+    for (int v = 0; v < nvar; ++v) {
+        const double x = src[v * G.vol + tid];
+        dst1[v * G.vol + tid] = x;
+        dst2[v * G.vol + tid] = x;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CFL limit and state check
 // ---------------------------------------------------------------------------

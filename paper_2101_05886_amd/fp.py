@@ -122,6 +122,7 @@ class Grid:
         return (self.ndim,) + tuple(reversed(ext))
 
     def work_shape(self):
+        """the RK3 workspace (see fp_work_bytes): three state-sized arrays"""
         return (3,) + self.state_shape()
 
 

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2101_05886_amd import fp
@@ -33,6 +34,7 @@ def test_sizes():
     assert fp.state_bytes(g) == 8 * 5 * n
     assert fp.metric_bytes(g) == 8 * 10 * n
     assert fp.work_bytes(g) == 3 * 8 * 5 * n
+    assert 8 * int(np.prod(g.work_shape())) == fp.work_bytes(g)
     assert fp.coord_bytes(g, 6) == 8 * 3 * (22 * 24 * 26)  # ghost 3 + 3 per side
     g2 = fp.Grid(2, (10, 12), 4)
     assert fp.state_bytes(g2) == 8 * 4 * 18 * 20
