@@ -7,6 +7,10 @@ region (metrics are computed once, outside it).  One "step" is one full
 third-order TVD Runge-Kutta step (three residual evaluations and updates),
 replayed from the library's captured step graph.
 
+Default workload (c4): 48 uneven O-grid blocks advanced together by the
+batched path, FP32-mixed reconstruction as `value`, FP64 timed beside it
+(`fp64`, `mixed_over_fp64`).  Single-block workloads: --workload c1/c2/c3/c3m.
+
 Prints ONE JSON line.  Extra fields: the per-kernel roofline of the dominant
 sweep kernel (timed with HIP events on the stream it runs on), the
 stage-level HBM figure of the method's compulsory traffic, and the FP64 CPU
@@ -84,6 +88,17 @@ WORKLOADS = {
                     "WENO5-JS with 2nd-order metrics, FP64",
                ndim=2, n=64, Y=2, recon="weno5", prec="fp64", L=20.0, amp=0.1, jitter=0.05,
                seed=1, mach=0.5, vortex=False, cfl=0.5),
+    "c5": dict(name="serving: Poisson stream of 500 solve requests (seed 5) at 0.8x the measured "
+                    "closed-loop capacity; grids 2D 64^2 to 3D 160^3 (log-uniform nodes), wavy periodic "
+                    "with a vortex or O-grid with frozen ghosts; Mach U(0.3, 2.0), angle U(0, 10) deg; "
+                    "200 RK3 steps each; WENO5-JS with 6th-order metrics, FP32-mixed; continuous batching",
+               ndim=3, Y=6, recon="weno5", prec="mixed", requests=500, seed=5, load=0.8,
+               capacity_requests=100, slots=64, round_steps=10),
+    "c4": dict(name="48 O-grid sector blocks (seed 4; n_theta 32..192, n_r 32..128, n_z 16..64; wall "
+                    "spacing 0.01 stretched x1.1; skew up to 30 deg), uniform Mach 3 along x with frozen "
+                    "free-stream ghosts, WENO5-JS with 6th-order metrics, batched: one persistent launch "
+                    "per sweep direction and RK stage, FP32-mixed (FP64 timed beside it)",
+               ndim=3, Y=6, recon="weno5", prec="mixed", mach=3.0, cfl=0.5, blocks=48, seed=4),
 }
 
 
@@ -127,6 +142,165 @@ def cpu_baseline(w, xyz, q, g, budget_s=20.0):
                       f"FP64 oracle (gcc -O2, OpenMP over grid lines), {el:.1f} s"}
 
 
+def c4_inputs(w):
+    """coordinates and states of the 48 O-grid blocks (host arrays)"""
+    from paper_2101_05886_amd import inputs as I
+    g, Y = 3, w["Y"]
+    out = []
+    for spec in I.multiblock_specs(w["blocks"], seed=w["seed"]):
+        xyz = I.ogrid_sector_block(spec.n, g, Y, spec.sector, spec.skew_deg, spec.rotation)
+        q = I.uniform_state(3, spec.n, g, 1.4, I.mach_velocity(w["mach"], [1.0, 0.0, 0.0]), 1.0)
+        out.append((list(spec.n), xyz, q))
+    return out, g
+
+
+def cpu_baseline_blocks(w, blocks, g, budget_s=20.0):
+    """FP64 oracle on the host: one RK3 step of as many of the blocks (in
+    order) as fit in about budget_s seconds (at least one)."""
+    import oracle as O
+    sc = O.Scheme(w["recon"], w["Y"], True)
+    nodes = 0
+    used = 0
+    el = 0.0
+    for n, xyz, q in blocks:
+        og = O.Grid(3, n, g, bc=[1, 1, 1])
+        met = O.metrics(og, w["Y"], xyz)
+        dt = O.max_dt(og, sc, met, q, w["cfl"])
+        t0 = time.perf_counter()
+        O.rk3_step(og, sc, met, q, dt)
+        el += time.perf_counter() - t0
+        nodes += int(np.prod(n))
+        used += 1
+        if el > budget_s * 0.5:
+            break
+    return {"value": nodes * 3 / el, "unit": "cell-stage updates/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"one RK3 step of each of the first {used} of the {len(blocks)} blocks "
+                      f"({nodes} nodes), FP64 oracle (gcc -O2, OpenMP over grid lines), {el:.1f} s"}
+
+
+def bench_batch(args, w):
+    import torch
+    from paper_2101_05886_amd import fp
+
+    blocks, g = c4_inputs(w)
+    dev = torch.device("cuda")
+    nodes = sum(int(np.prod(n)) for n, _, _ in blocks)
+    res = {}
+    per_kernel = {}
+    for prec in ("fp64", "mixed"):
+        sc = fp.Scheme(w["recon"], w["Y"], True, precision=prec)
+        ent = []
+        for n, xyz, q in blocks:
+            G = fp.Grid(3, n, g, bc=[1, 1, 1])
+            met = fp.metrics(G, w["Y"], torch.from_numpy(xyz).to(dev))
+            qg = torch.from_numpy(q).to(dev)
+            work = torch.zeros(G.work_shape(), dtype=torch.float64, device=dev)
+            dt = float(fp.max_dt(G, sc, met, qg, w["cfl"]).item())
+            ent.append((G, met, qg, work, dt))
+        b = fp.Batch(sc, len(ent))
+        b.set(ent)
+        seg = b.autotune()
+        b.solve(max(args.warmup, 1))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.solve(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        flag_ok = True
+        for G, met, qg, work, dt in ent:
+            flag_ok = flag_ok and int(fp.check_state(G, sc, qg).item()) == 0
+        # per-launch durations of one instrumented step (HIP events on the
+        # stream the batched kernels run on)
+        prof = b.profile_step()
+        kinds = {}
+        for ndim, kind, t in prof:
+            kinds.setdefault(kind, []).append(t)
+        per_kernel[prec] = {k: sum(v) / len(v) for k, v in kinds.items()}
+        res[prec] = dict(value=nodes * 3 * args.steps / (ms * 1e-3), ms_step=ms / args.steps, seg=seg,
+                         ok=flag_ok)
+        b.close()
+        del ent
+        torch.cuda.empty_cache()
+    names = {0: "kb_sweep_x", 1: "kb_sweep_wg<eta>", 2: "kb_sweep_wg<zeta>", 3: "kb_frozen_ghosts"}
+    pk = per_kernel["mixed"]
+    dom = max((k for k in pk if k != 3), key=pk.get)
+    ftab, fcur = counter_table(FLOPS_FILE)
+    ttab, tcur = counter_table(TRAFFIC_FILE)
+    fpf = ftab.get(f"{w['recon']}/3d/mixed")
+    traffic = ttab.get(f"c4/{names[dom]}") if tcur else None
+    achieved = fpf * nodes / (pk[dom] * 1e-3) / 1e12 if fpf else None
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": traffic,
+            "kernel": names[dom], "kernel_ms": pk[dom], "flops_per_face": fpf, "counters_current": fcur,
+            "traffic_gbs": traffic / (pk[dom] * 1e-3) / 1e9 if traffic else None,
+            "kernel_ms_by_kind": {names[k]: round(v, 4) for k, v in sorted(pk.items())},
+            "kernel_ms_by_kind_fp64": {names[k]: round(v, 4) for k, v in sorted(per_kernel["fp64"].items())}}
+    value = res["mixed"]["value"]
+    stage_gbs = STAGE_BYTES[3] * value / 1e9
+    out = {
+        "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["mixed"]["ms_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 state, f32 reconstruction", "data": "synthetic",
+        "config": {"workload": w["name"], "blocks": len(blocks), "nodes": nodes, "metric_order": w["Y"],
+                   "recon": w["recon"], "precision": "mixed", "segment": res["mixed"]["seg"]},
+        "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_step"],
+                 "segment": res["fp64"]["seg"]},
+        "mixed_over_fp64": value / res["fp64"]["value"],
+        "roofline": roof,
+        "hbm_stage": {"bytes_per_cell_stage": STAGE_BYTES[3], "achieved": stage_gbs,
+                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS},
+        "state_ok": res["mixed"]["ok"] and res["fp64"]["ok"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_blocks(w, blocks, g)
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, w):
+    import torch
+    from paper_2101_05886_amd import fp
+    from paper_2101_05886_amd import serve as S
+
+    sc = fp.Scheme(w["recon"], w["Y"], True, precision=w["prec"])
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.85 * total) - (8 << 30)
+
+    def run(reqs):
+        be = S.GpuBackend(sc, w["slots"])
+        try:
+            st, _ = S.Scheduler(be, budget, w["slots"], w["round_steps"]).run(reqs)
+        finally:
+            be.close()
+        return st
+
+    # closed loop (all requests at t = 0) on the first requests of the
+    # stream: the capacity the open-loop arrival rate is scaled from
+    closed = run(S.make_requests(w["capacity_requests"], seed=w["seed"], rate=None))
+    cap = closed.summary()["requests_per_s"]
+    rate = w["load"] * cap
+    st = run(S.make_requests(w["requests"], seed=w["seed"], rate=rate))
+    s = st.summary()
+    out = {
+        "metric": "cell-stage updates/s", "value": s["cell_stage_per_s"], "unit": "cell-stage updates/s",
+        "n_gpus": 1, "steps": 200, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 state, f32 reconstruction", "data": "synthetic",
+        "config": {"workload": w["name"], "requests": w["requests"], "slots": w["slots"],
+                   "round_steps": w["round_steps"], "hbm_budget_bytes": budget},
+        "serving": {"p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
+                    "requests_per_s": s["requests_per_s"], "mean_queue_wait_s": s["mean_queue_wait_s"],
+                    "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": cap,
+                    "closed_loop_cell_stage_per_s": closed.summary()["cell_stage_per_s"],
+                    "makespan_s": s["makespan_s"], "rounds": s["rounds"], "peak_active": s["peak_active"],
+                    "peak_bytes": s["peak_bytes"]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 COPY_BYTES = 1 << 30
 
 
@@ -146,7 +320,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -166,6 +340,12 @@ def main():
     from paper_2101_05886_amd import fp
 
     w = WORKLOADS[args.workload]
+    if "blocks" in w:
+        bench_batch(args, w)
+        return
+    if "requests" in w:
+        bench_serve(args, w)
+        return
     xyz, q, g = make_inputs(w)
     ndim, n, Y = w["ndim"], w["n"], w["Y"]
     G = fp.Grid(ndim, n, g)

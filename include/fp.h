@@ -162,6 +162,71 @@ fp_status fp_max_dt(const fp_grid *grid, const fp_scheme *scheme, const double *
 fp_status fp_check_state(const fp_grid *grid, const fp_scheme *scheme, const double *q,
                          int32_t *flag_dev, void *stream);
 
+/* ---- Batches: many independent blocks advanced in shared launches ----
+ *
+ * A batch advances many blocks, of uneven sizes and possibly mixed 2D/3D,
+ * with one scheme, by the RK3 step of fp_rk3_step (Sec. 2.2), each block
+ * with its own dt.  Per RK stage every sweep direction is ONE persistent
+ * launch over a (block, tile) work list of all blocks of a dimensionality;
+ * a step is 1 + 3 x ndim such launches, captured once into a HIP graph by
+ * fp_batch_solve.  Per block the arithmetic is that of fp_rk3_step, and the
+ * result is bitwise the same as advancing the block alone.
+ *
+ * Ownership: the batch owns its device work-list tables and a pinned host
+ * staging copy (allocated by fp_batch_create, freed by fp_batch_destroy);
+ * the blocks' arrays stay the caller's.  fp_batch_set, fp_batch_rk3_step,
+ * fp_batch_solve and fp_batch_autotune allocate nothing (the first
+ * fp_batch_solve of a given mix of 2D/3D parts captures a graph).  All calls
+ * on one batch must use one stream and one thread at a time; different
+ * batches are independent.  A block's arrays must not be freed while work of
+ * a step that uses them is pending. */
+typedef struct {
+    fp_grid grid;
+    const double *met; /* fp_metric_bytes(&grid), from fp_metrics */
+    double *q;         /* fp_state_bytes(&grid), advanced in place */
+    double *work;      /* fp_work_bytes(&grid), the block's own workspace */
+    double dt;         /* > 0 */
+} fp_block;
+
+typedef struct fp_batch fp_batch;
+
+/* A batch for up to max_blocks blocks (1 .. 65536) of `scheme`, on the
+ * current HIP device.  FP_ENOMEM if the tables cannot be allocated. */
+fp_status fp_batch_create(const fp_scheme *scheme, int32_t max_blocks, fp_batch **out);
+
+/* Replaces the batch's blocks (host array of nblocks entries, 0 .. max
+ * blocks; the entries are copied).  Every block is validated as in
+ * fp_rk3_step; on an error nothing changes.  The new work list is copied to
+ * the device in stream order, so steps enqueued earlier still see the old
+ * list.  Graphs captured by fp_batch_solve stay valid. */
+fp_status fp_batch_set(fp_batch *batch, const fp_block *blocks, int32_t nblocks, void *stream);
+
+/* One RK3 step of every block of the batch. */
+fp_status fp_batch_rk3_step(fp_batch *batch, void *stream);
+
+/* nsteps RK3 steps of every block, replaying the batch's step graph. */
+fp_status fp_batch_solve(fp_batch *batch, int64_t nsteps, void *stream);
+
+/* Chooses the eta/zeta segment length of the batch's work list by timing
+ * the sweeps of RK stage 1 for a set of candidates on the current blocks
+ * (synchronises the stream; the blocks' workspaces are overwritten, q is
+ * not).  The choice is kept for later fp_batch_set calls and written to
+ * *segment if non-NULL. */
+fp_status fp_batch_autotune(fp_batch *batch, int32_t *segment, void *stream);
+
+/* Instrumented step: one RK3 step of every block, exactly as
+ * fp_batch_rk3_step, with a HIP event recorded on `stream` after each of its
+ * launches; synchronises and writes each launch's duration in milliseconds
+ * to kernel_ms[i] and its kind to kernel_kind[i] = 16 * ndim + k (k = 0 xi
+ * sweep, 1 eta sweep, 2 zeta sweep, 3 frozen-ghost copy), in launch order,
+ * and the number of launches (at most 20) to *n_kernels.  FP_EINVAL if
+ * max_kernels is too small (nothing enqueued). */
+fp_status fp_batch_profile_step(fp_batch *batch, float *kernel_ms, int32_t *kernel_kind,
+                                int32_t max_kernels, int32_t *n_kernels, void *stream);
+
+/* Frees the batch (after synchronising its pending work). NULL is a no-op. */
+void fp_batch_destroy(fp_batch *batch);
+
 /* Frees the cached step graphs. */
 void fp_release_cache(void);
 

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "fp.h"
 #include "fp_kernels.hpp"
@@ -20,6 +21,8 @@ namespace fpk {
 #define FP_DECL_GET(P, R)                                           \
     stage_fn get_stage_p##P##_r##R(int ndim, int Y);                \
     dir_fn get_dir_p##P##_r##R(int ndim, int Y);                    \
+    batch_stage_fn get_batch_stage_p##P##_r##R(int ndim, int Y);    \
+    batch_occ_fn get_batch_occ_p##P##_r##R(int ndim, int Y);        \
     faceflux_fn get_faceflux_p##P##_r##R(int ndim, int dir, int Y);
 FP_DECL_GET(0, 0)
 FP_DECL_GET(0, 1)
@@ -35,6 +38,16 @@ stage_fn get_stage_fn(int ndim, int recon, int Y, int prec) {
 dir_fn get_dir_fn(int ndim, int recon, int Y, int prec) {
     if (prec == 0) return recon == 0 ? get_dir_p0_r0(ndim, Y) : get_dir_p0_r1(ndim, Y);
     return recon == 0 ? get_dir_p1_r0(ndim, Y) : get_dir_p1_r1(ndim, Y);
+}
+
+batch_stage_fn get_batch_stage_fn(int ndim, int recon, int Y, int prec) {
+    if (prec == 0) return recon == 0 ? get_batch_stage_p0_r0(ndim, Y) : get_batch_stage_p0_r1(ndim, Y);
+    return recon == 0 ? get_batch_stage_p1_r0(ndim, Y) : get_batch_stage_p1_r1(ndim, Y);
+}
+
+batch_occ_fn get_batch_occ_fn(int ndim, int recon, int Y, int prec) {
+    if (prec == 0) return recon == 0 ? get_batch_occ_p0_r0(ndim, Y) : get_batch_occ_p0_r1(ndim, Y);
+    return recon == 0 ? get_batch_occ_p1_r0(ndim, Y) : get_batch_occ_p1_r1(ndim, Y);
 }
 
 faceflux_fn get_faceflux_fn(int ndim, int dir, int recon, int Y, int prec) {
@@ -261,6 +274,131 @@ struct GraphKey {
 std::mutex g_mu;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
 std::map<int, hipStream_t> g_capture_streams;
+
+// ---- batches ----
+
+constexpr int kSegTargets[] = {15, 23, 31, 47, 63, 95, 127};
+constexpr int kSegDefault = 31;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct fp_batch {
+    int dev = 0;
+    fp_scheme sch{};
+    SchemeK sk{};
+    int cap = 0;
+    int seg = kSegDefault;  // eta / zeta segment length target
+    size_t part_bytes = 0;  // one part's tables: [nblk | start | blocks]
+    char* dmem = nullptr;   // device tables, part 0 = 2D blocks, part 1 = 3D blocks
+    char* hstage = nullptr; // pinned host image of dmem
+    hipEvent_t staged = nullptr;
+    bool pending = false;   // a staging copy may still read hstage
+    std::vector<fp_block> blocks;
+    int nblk[2] = {0, 0};
+    BTab tab[2]{};
+    int grid[2][BK_KINDS]{};
+    batch_stage_fn fn[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};  // by mask of non-empty parts
+    hipStream_t cs = nullptr;
+};
+
+namespace {
+
+size_t start_offset() { return 256; }
+size_t blk_offset(int cap) { return 256 + align256(sizeof(long) * BK_KINDS * (size_t)(cap + 1)); }
+
+int seg_len(int nd, int target) {
+    const int nseg = (nd + target - 1) / target;
+    return (nd + nseg - 1) / nseg;
+}
+
+// Host image of the tables of both parts for `blocks` (already validated).
+void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, char* img, int nblk[2]) {
+    for (int p = 0; p < 2; ++p) {
+        char* base = img + p * b->part_bytes;
+        long* start = reinterpret_cast<long*>(base + start_offset());
+        BBlock* blk = reinterpret_cast<BBlock*>(base + blk_offset(b->cap));
+        const int ndim = p == 0 ? 2 : 3;
+        int n = 0;
+        long acc[BK_KINDS] = {0, 0, 0, 0};
+        for (const fp_block& fb : blocks) {
+            if (fb.grid.ndim != ndim) continue;
+            BBlock& B = blk[n];
+            std::memset(&B, 0, sizeof B);
+            B.G = make_geo(&fb.grid);
+            const size_t se = (size_t)(ndim + 2) * B.G.vol;
+            B.met = fb.met;
+            B.q = fb.q;
+            B.A = fb.work;
+            B.B = fb.work + se;
+            B.R = fb.work + 2 * se;
+            B.dt = fb.dt;
+            B.S[0] = 0;
+            B.S[1] = seg_len(B.G.n[1], b->seg);
+            B.S[2] = ndim == 3 ? seg_len(B.G.n[2], b->seg) : 0;
+            bool frozen = false;
+            for (int d = 0; d < ndim; ++d) frozen = frozen || fb.grid.bc[d] == FP_BC_FROZEN;
+            long items[BK_KINDS];
+            items[BK_X] = (sweep_x_waves(B.G.n) + 3) / 4;
+            items[BK_ETA] = sweep_wg_items(B.G.n, 1, B.S[1]);
+            items[BK_ZETA] = ndim == 3 ? sweep_wg_items(B.G.n, 2, B.S[2]) : 0;
+            items[BK_GHOST] = frozen ? (B.G.vol + 255) / 256 : 0;
+            for (int k = 0; k < BK_KINDS; ++k) {
+                start[k * (b->cap + 1) + n] = acc[k];
+                acc[k] += items[k];
+            }
+            ++n;
+        }
+        for (int k = 0; k < BK_KINDS; ++k) start[k * (b->cap + 1) + n] = acc[k];
+        *reinterpret_cast<int*>(base) = n;
+        nblk[p] = n;
+    }
+}
+
+// Copy the tables of `blocks` to the device in stream order.
+fp_status upload_tables(fp_batch* b, const std::vector<fp_block>& blocks, hipStream_t s) {
+    if (b->pending) {
+        hipError_t e = hipEventSynchronize(b->staged);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        b->pending = false;
+    }
+    int nblk[2];
+    build_tables(b, blocks, b->hstage, nblk);
+    hipError_t e = hipMemcpyAsync(b->dmem, b->hstage, 2 * b->part_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch tables)");
+    e = hipEventRecord(b->staged, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    b->pending = true;
+    b->nblk[0] = nblk[0];
+    b->nblk[1] = nblk[1];
+    return FP_OK;
+}
+
+hipError_t run_batch_step(const fp_batch* b, int mask, hipStream_t s) {
+    for (int p = 0; p < 2; ++p) {
+        if (!(mask & (1 << p))) continue;
+        const int ndim = p == 0 ? 2 : 3;
+        hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p], ndim);
+        for (int k = 0; k < 3; ++k) {
+            hipError_t e = b->fn[p](b->tab[p], b->sk, k, b->grid[p], -1, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipGetLastError();
+}
+
+int batch_mask(const fp_batch* b) { return (b->nblk[0] > 0 ? 1 : 0) | (b->nblk[1] > 0 ? 2 : 0); }
+
+fp_status check_batch(const fp_batch* b) {
+    if (!b) return fail(FP_EINVAL, "batch is NULL");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != b->dev) return fail(FP_EINVAL, "batch was created on device %d, current device is %d", b->dev, dev);
+    return FP_OK;
+}
 
 }  // namespace
 
@@ -517,6 +655,234 @@ fp_status fp_check_state(const fp_grid* g, const fp_scheme* sch, const double* q
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "fp_check_state launch");
     return FP_OK;
+}
+
+fp_status fp_batch_create(const fp_scheme* sch, int32_t max_blocks, fp_batch** out) {
+    if (!out) return fail(FP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_blocks < 1 || max_blocks > 65536) return fail(FP_EINVAL, "max_blocks must be in [1, 65536]");
+    fp_grid g3{};
+    g3.ndim = 3;
+    g3.n[0] = g3.n[1] = g3.n[2] = 8;
+    g3.ghost = sch ? (sch->metric_order == 8 ? 4 : 3) : 3;
+    fp_status st = check_scheme(&g3, sch);
+    if (st) return st;
+    fp_batch* b = new fp_batch();
+    b->sch = *sch;
+    b->sk = make_sk(sch);
+    b->cap = max_blocks;
+    b->part_bytes = align256(blk_offset(max_blocks) + sizeof(BBlock) * (size_t)max_blocks);
+    hipError_t e = hipGetDevice(&b->dev);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->dmem, 2 * b->part_bytes);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(FP_ENOMEM, "batch tables: %s", hipGetErrorString(e));
+    }
+    e = hipHostMalloc((void**)&b->hstage, 2 * b->part_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        hipFree(b->dmem);
+        delete b;
+        return fail(FP_ENOMEM, "batch staging: %s", hipGetErrorString(e));
+    }
+    std::memset(b->hstage, 0, 2 * b->part_bytes);
+    e = hipMemcpy(b->dmem, b->hstage, 2 * b->part_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking);
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->dev);
+    if (e != hipSuccess) {
+        fp_batch_destroy(b);
+        return hip_fail(e, "fp_batch_create");
+    }
+    for (int p = 0; p < 2; ++p) {
+        const int ndim = p == 0 ? 2 : 3;
+        char* base = b->dmem + p * b->part_bytes;
+        b->tab[p].nblk = reinterpret_cast<const int*>(base);
+        b->tab[p].start = reinterpret_cast<const long*>(base + start_offset());
+        b->tab[p].blk = reinterpret_cast<const BBlock*>(base + blk_offset(max_blocks));
+        b->tab[p].cap = max_blocks;
+        b->fn[p] = get_batch_stage_fn(ndim, sch->recon, sch->metric_order, sch->precision);
+        batch_occ_fn occ = get_batch_occ_fn(ndim, sch->recon, sch->metric_order, sch->precision);
+        if (!b->fn[p] || !occ) {
+            fp_batch_destroy(b);
+            return fail(FP_EUNSUPPORTED, "no batched kernel for this scheme");
+        }
+        for (int k = 0; k < 3; ++k) {
+            const int per_cu = occ(k);
+            b->grid[p][k] = (per_cu > 0 ? per_cu : 1) * cus;
+        }
+        b->grid[p][BK_GHOST] = 4 * cus;
+    }
+    *out = b;
+    return FP_OK;
+}
+
+fp_status fp_batch_set(fp_batch* b, const fp_block* blocks, int32_t nblocks, void* stream) {
+    fp_status st = check_batch(b);
+    if (st) return st;
+    if (nblocks < 0 || nblocks > b->cap) return fail(FP_EINVAL, "nblocks must be in [0, %d]", b->cap);
+    if (nblocks > 0 && !blocks) return fail(FP_EINVAL, "blocks is NULL");
+    for (int i = 0; i < nblocks; ++i) {
+        const fp_block& fb = blocks[i];
+        st = check_grid(&fb.grid);
+        if (st) return fail(st, "block %d: %s", i, g_err.c_str());
+        st = check_scheme(&fb.grid, &b->sch);
+        if (st) return fail(st, "block %d: %s", i, g_err.c_str());
+        if (!fb.met || !fb.q || !fb.work) return fail(FP_EINVAL, "block %d: NULL array", i);
+        if (!(fb.dt > 0.0)) return fail(FP_EINVAL, "block %d: dt must be positive", i);
+    }
+    std::vector<fp_block> v(blocks, blocks + nblocks);
+    st = upload_tables(b, v, (hipStream_t)stream);
+    if (st) return st;
+    b->blocks.swap(v);
+    return FP_OK;
+}
+
+fp_status fp_batch_rk3_step(fp_batch* b, void* stream) {
+    fp_status st = check_batch(b);
+    if (st) return st;
+    hipError_t e = run_batch_step(b, batch_mask(b), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fp_batch_rk3_step launch");
+    return FP_OK;
+}
+
+fp_status fp_batch_solve(fp_batch* b, int64_t nsteps, void* stream) {
+    fp_status st = check_batch(b);
+    if (st) return st;
+    if (nsteps < 0) return fail(FP_EINVAL, "nsteps must be >= 0");
+    const int mask = batch_mask(b);
+    if (nsteps == 0 || mask == 0) return FP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (!b->graph[mask]) {
+        e = hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = run_batch_step(b, mask, b->cs);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(b->cs, &graph);
+        if (le != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return hip_fail(le, "fp_batch_solve capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        b->graph[mask] = exec;
+    }
+    for (int64_t i = 0; i < nsteps; ++i) {
+        e = hipGraphLaunch(b->graph[mask], s);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    return FP_OK;
+}
+
+fp_status fp_batch_autotune(fp_batch* b, int32_t* segment, void* stream) {
+    fp_status st = check_batch(b);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int mask = batch_mask(b);
+    if (mask == 0) {
+        if (segment) *segment = b->seg;
+        return FP_OK;
+    }
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    int best = b->seg;
+    float best_ms = -1.0f;
+    for (int T : kSegTargets) {
+        b->seg = T;
+        st = upload_tables(b, b->blocks, s);
+        if (st) break;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, s);
+            for (int p = 0; p < 2 && e == hipSuccess; ++p)
+                if (mask & (1 << p)) e = b->fn[p](b->tab[p], b->sk, 0, b->grid[p], -1, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (rep > 0) ms += t;  // the first repetition warms up
+        }
+        if (e != hipSuccess) break;
+        if (best_ms < 0.0f || ms < best_ms) {
+            best_ms = ms;
+            best = T;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    if (e != hipSuccess) return hip_fail(e, "fp_batch_autotune");
+    b->seg = best;
+    st = upload_tables(b, b->blocks, s);
+    if (st) return st;
+    if (segment) *segment = best;
+    return FP_OK;
+}
+
+fp_status fp_batch_profile_step(fp_batch* b, float* kernel_ms, int32_t* kernel_kind, int32_t max_kernels,
+                                int32_t* n_kernels, void* stream) {
+    fp_status st = check_batch(b);
+    if (st) return st;
+    if (!kernel_ms || !kernel_kind || !n_kernels) return fail(FP_EINVAL, "NULL output");
+    hipStream_t s = (hipStream_t)stream;
+    const int mask = batch_mask(b);
+    // the launches of one step, in order: (part, kind, stage)
+    int plan[2 * 10][3];
+    int n = 0;
+    for (int p = 0; p < 2; ++p) {
+        if (!(mask & (1 << p))) continue;
+        const int ndim = p == 0 ? 2 : 3;
+        plan[n][0] = p, plan[n][1] = BK_GHOST, plan[n][2] = -1, ++n;
+        for (int k = 0; k < 3; ++k)
+            for (int kind = 0; kind < ndim; ++kind) plan[n][0] = p, plan[n][1] = kind, plan[n][2] = k, ++n;
+    }
+    if (n > max_kernels) return fail(FP_EINVAL, "max_kernels must be >= %d", n);
+    hipEvent_t ev[2 * 10 + 1];
+    hipError_t e = hipSuccess;
+    int made = 0;
+    while (made <= n) {
+        e = hipEventCreate(&ev[made]);
+        if (e != hipSuccess) break;
+        ++made;
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const int p = plan[i][0], kind = plan[i][1], k = plan[i][2];
+        if (kind == BK_GHOST)
+            hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p],
+                               p == 0 ? 2 : 3);
+        else
+            e = b->fn[p](b->tab[p], b->sk, k, b->grid[p], kind, s);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(ev[i + 1], s);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[n]);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        e = hipEventElapsedTime(&kernel_ms[i], ev[i], ev[i + 1]);
+        kernel_kind[i] = (plan[i][0] == 0 ? 2 : 3) * 16 + plan[i][1];
+    }
+    for (int i = 0; i < made; ++i) hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return hip_fail(e, "fp_batch_profile_step");
+    *n_kernels = n;
+    return FP_OK;
+}
+
+void fp_batch_destroy(fp_batch* b) {
+    if (!b) return;
+    hipDeviceSynchronize();
+    for (auto& gx : b->graph)
+        if (gx) hipGraphExecDestroy(gx);
+    if (b->cs) hipStreamDestroy(b->cs);
+    if (b->staged) hipEventDestroy(b->staged);
+    if (b->hstage) hipHostFree(b->hstage);
+    if (b->dmem) hipFree(b->dmem);
+    delete b;
 }
 
 void fp_release_cache(void) {

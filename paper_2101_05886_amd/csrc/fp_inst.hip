@@ -28,7 +28,7 @@ void launch_wg(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
     constexpr int OTH = DIR == 1 ? 2 : 1;
     const long lblocks = ((long)a.G.n[0] * a.G.n[OTH] + 63) / 64;
     hipLaunchKernelGGL((k_sweep_wg<DIM, DIR, R, Y, P>), dim3((unsigned)(lblocks * a.nseg[DIR])),
-                       dim3(256), 0, s, a.G, a.sk, a.met, a.qs, ep, a.S[DIR], a.nseg[DIR]);
+                       dim3(256), 0, s, a.G, a.sk, a.met, a.qs, ep, a.S[DIR]);
 }
 
 template <int DIM, int Y>
@@ -106,6 +106,54 @@ faceflux_fn pick_ff(int Y) {
     return nullptr;
 }
 
+template <int DIM, int Y>
+hipError_t run_batch_stage(const BTab& t, const SchemeK& sk, int stage, const int grid[3], int only,
+                           hipStream_t s) {
+    if (only < 0 || only == BK_X)
+        hipLaunchKernelGGL((kb_sweep_x<DIM, R, Y, P>), dim3(grid[0]), dim3(256), 0, s, t, sk, stage);
+    if (only < 0 || only == BK_ETA)
+        hipLaunchKernelGGL((kb_sweep_wg<DIM, 1, R, Y, P>), dim3(grid[1]), dim3(256), 0, s, t, sk, stage);
+    if constexpr (DIM == 3)
+        if (only < 0 || only == BK_ZETA)
+            hipLaunchKernelGGL((kb_sweep_wg<3, 2, R, Y, P>), dim3(grid[2]), dim3(256), 0, s, t, sk, stage);
+    return hipGetLastError();
+}
+
+template <int DIM, int Y>
+int batch_occ(int kind) {
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    if (kind == BK_X)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_sweep_x<DIM, R, Y, P>, 256, 0);
+    else if (kind == BK_ETA || DIM == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_sweep_wg<DIM, 1, R, Y, P>, 256, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kb_sweep_wg<DIM, DIM - 1, R, Y, P>, 256, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+template <int DIM>
+batch_stage_fn pick_batch(int Y) {
+    switch (Y) {
+    case 2: return &run_batch_stage<DIM, 2>;
+    case 4: return &run_batch_stage<DIM, 4>;
+    case 6: return &run_batch_stage<DIM, 6>;
+    case 8: return &run_batch_stage<DIM, 8>;
+    }
+    return nullptr;
+}
+
+template <int DIM>
+batch_occ_fn pick_occ(int Y) {
+    switch (Y) {
+    case 2: return &batch_occ<DIM, 2>;
+    case 4: return &batch_occ<DIM, 4>;
+    case 6: return &batch_occ<DIM, 6>;
+    case 8: return &batch_occ<DIM, 8>;
+    }
+    return nullptr;
+}
+
 }  // namespace
 
 stage_fn FP_CAT(get_stage, FP_SUFFIX)(int ndim, int Y) {
@@ -114,6 +162,14 @@ stage_fn FP_CAT(get_stage, FP_SUFFIX)(int ndim, int Y) {
 
 dir_fn FP_CAT(get_dir, FP_SUFFIX)(int ndim, int Y) {
     return ndim == 3 ? pick_dir<3>(Y) : pick_dir<2>(Y);
+}
+
+batch_stage_fn FP_CAT(get_batch_stage, FP_SUFFIX)(int ndim, int Y) {
+    return ndim == 3 ? pick_batch<3>(Y) : pick_batch<2>(Y);
+}
+
+batch_occ_fn FP_CAT(get_batch_occ, FP_SUFFIX)(int ndim, int Y) {
+    return ndim == 3 ? pick_occ<3>(Y) : pick_occ<2>(Y);
 }
 
 faceflux_fn FP_CAT(get_faceflux, FP_SUFFIX)(int ndim, int dir, int Y) {

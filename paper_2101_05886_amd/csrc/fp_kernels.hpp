@@ -133,14 +133,14 @@ using char_t = typename std::conditional<PREC == 1, float, double>::type;
 // xi sweep: 64 lanes evaluate 64 consecutive faces of the flattened face index
 // (faces of consecutive xi-lines one after another); waves overlap by one face
 // so that every lane but the first takes its left neighbour's flux by a lane
-// shift and forms the flux difference of its node.
+// shift and forms the flux difference of its node.  `wave` numbers the waves
+// of one block; all 64 lanes must call this (the lane shift).
 template <int DIM, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK sk,
-                                                               const double* __restrict__ met,
-                                                               const double* qs, EpiK ep) {
+__device__ __forceinline__ void sweep_x_wave(const GeoK& G, const SchemeK& sk,
+                                             const double* __restrict__ met, const double* qs,
+                                             const EpiK& ep, long wave) {
     constexpr int NV = DIM + 2;
     const int lane = threadIdx.x & 63;
-    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     const long F = wave * 63 + lane;
     const int nf = G.n[0] + 1;
     const long total = (long)nf * G.n[1] * G.n[2];
@@ -165,28 +165,32 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK s
     if (active && lane > 0 && f > 0) epilogue<NV>(ep, G.vol, lb + (f - 1), d);
 }
 
+// Waves of the xi sweep of one block (four per workgroup of 256 threads).
+inline long sweep_x_waves(const int n[3]) { return ((long)(n[0] + 1) * n[1] * n[2] + 62) / 63; }
+
 // eta / zeta sweeps: a workgroup of four waves owns 64 grid lines along DIR
 // (consecutive in the flattened (i, other) index, so loads are coalesced)
-// and one segment [k0, k1) of them.  Per iteration wave w evaluates the face
-// f+1/2, f = k0 - 1 + 4 it + w, on its 64 lines; the fluxes go to LDS (three
-// rotating buffers of four rows, so one barrier per iteration suffices) and
-// wave w then forms node f's difference F'_{f+1/2} - F'_{f-1/2}.  Every
-// thread runs the same number of iterations (no early exit before a barrier).
+// and one segment [k0, k1) of S nodes of them; work item `item` of a block
+// is (line block = item % lblocks, segment = item / lblocks).  Per iteration
+// wave w evaluates the face f+1/2, f = k0 - 1 + 4 it + w, on its 64 lines;
+// the fluxes go to the LDS ring `fl` (three rotating buffers of four rows,
+// so one barrier per iteration suffices) and wave w then forms node f's
+// difference F'_{f+1/2} - F'_{f-1/2}.  Every thread of the workgroup runs
+// the same number of iterations (no early exit before a barrier).  A caller
+// that reuses `fl` for another item must synchronise the workgroup first.
 template <int DIM, int DIR, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK sk,
-                                                                const double* __restrict__ met,
-                                                                const double* qs, EpiK ep, int S,
-                                                                int nseg) {
+__device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
+                                              const double* __restrict__ met, const double* qs,
+                                              const EpiK& ep, int S, long item,
+                                              double (*fl)[4][DIM + 2][64]) {
     constexpr int NV = DIM + 2;
     constexpr int OTH = DIR == 1 ? 2 : 1;
-    __shared__ double fl[3][4][NV][64];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const long nlines = (long)G.n[0] * G.n[OTH];
     const long lblocks = (nlines + 63) / 64;
-    const long blk = blockIdx.x;
-    const long lineblk = blk % lblocks;
-    const int seg = (int)(blk / lblocks);
+    const long lineblk = item % lblocks;
+    const int seg = (int)(item / lblocks);
     const long line = lineblk * 64 + lane;
     const bool lane_ok = line < nlines;
     const int i = lane_ok ? (int)(line % G.n[0]) : 0;
@@ -217,6 +221,134 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK 
             for (int v = 0; v < NV; ++v) d[v] = F[v] - fl[pb][pr][v][lane];
             epilogue<NV>(ep, G.vol, lb + (long)f * G.sd[DIR], d);
         }
+    }
+}
+
+// Work items (workgroups) of the eta / zeta sweep of one block.
+inline long sweep_wg_items(const int n[3], int dir, int S) {
+    const int oth = dir == 1 ? 2 : 1;
+    const long lblocks = ((long)n[0] * n[oth] + 63) / 64;
+    return lblocks * ((n[dir] + S - 1) / S);
+}
+
+template <int DIM, int RECON, int Y, int PREC>
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK sk,
+                                                               const double* __restrict__ met,
+                                                               const double* qs, EpiK ep) {
+    sweep_x_wave<DIM, RECON, Y, PREC>(G, sk, met, qs, ep, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
+template <int DIM, int DIR, int RECON, int Y, int PREC>
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK sk,
+                                                                const double* __restrict__ met,
+                                                                const double* qs, EpiK ep, int S) {
+    __shared__ double fl[3][4][DIM + 2][64];
+    sweep_wg_item<DIM, DIR, RECON, Y, PREC>(G, sk, met, qs, ep, S, blockIdx.x, fl);
+}
+
+// ---------------------------------------------------------------------------
+// batches: many blocks (of one dimensionality and scheme) in shared launches
+// ---------------------------------------------------------------------------
+
+// One block of a batch as the batched kernels see it.
+struct BBlock {
+    GeoK G;
+    const double* met;
+    double* q;  // Q^n, and the output of RK stage 3
+    double* A;  // RK stage registers and residual accumulator (the workspace)
+    double* B;
+    double* R;
+    double dt;
+    int S[3];  // eta / zeta segment lengths
+};
+
+// Kinds of work items of a batched RK step.
+enum { BK_X = 0, BK_ETA = 1, BK_ZETA = 2, BK_GHOST = 3, BK_KINDS = 4 };
+
+// Work-item table of a batch, in device memory.  The number of blocks and
+// the prefix sums are read by the kernels at run time, so a captured graph
+// stays valid when the table's contents change:
+//   *nblk                      blocks in use;
+//   start[k * (cap + 1) + b]   first item of block b in kind k; entry nblk is
+//                              the kind's total;
+//   blk[b]                     the block.
+struct BTab {
+    const int* nblk;
+    const long* start;
+    const BBlock* blk;
+    int cap;
+};
+
+// Largest b in [0, nblk) with st[b] <= item (blocks without items of a kind
+// have st[b] == st[b + 1] and are skipped).
+__device__ __forceinline__ int find_block(const long* st, int nblk, long item) {
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st[mid] <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ const double* stage_in(const BBlock& b, int stage) {
+    return stage == 0 ? b.q : (stage == 1 ? b.A : b.B);
+}
+
+// The epilogue of a sweep of RK stage `stage` (TVD RK3 in Shu-Osher form:
+// stage 1 writes A, stage 2 B, stage 3 q), the same values the single-block
+// driver uses.
+__device__ __forceinline__ EpiK stage_epi(const BBlock& b, int stage, int mode, int ndim) {
+    EpiK e;
+    e.mode = mode;
+    e.stage0 = stage == 0;
+    e.R = b.R;
+    e.out = stage == 0 ? b.A : (stage == 1 ? b.B : b.q);
+    e.metV = b.met + (ndim == 3 ? 9 : 4) * b.G.vol;
+    e.qin = stage_in(b, stage);
+    e.qn = b.q;
+    e.dt = b.dt;
+    e.a = stage == 0 ? 0.0 : (stage == 1 ? 3.0 / 4.0 : 1.0 / 3.0);
+    e.b = stage == 0 ? 1.0 : (stage == 1 ? 1.0 / 4.0 : 2.0 / 3.0);
+    return e;
+}
+
+// Persistent batched xi sweep of one RK stage: workgroup w takes items w,
+// w + gridDim.x, ... of the batch's xi items (one item = four waves of one
+// block).
+template <int DIM, int RECON, int Y, int PREC>
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(BTab t, SchemeK sk, int stage) {
+    const int nblk = *t.nblk;
+    const long* st = t.start + BK_X * (t.cap + 1);
+    const long total = st[nblk];
+    for (long item = blockIdx.x; item < total; item += gridDim.x) {
+        const int b = find_block(st, nblk, item);
+        const BBlock& B = t.blk[b];
+        const EpiK ep = stage_epi(B, stage, EPI_FIRST, DIM);
+        sweep_x_wave<DIM, RECON, Y, PREC>(B.G, sk, B.met, stage_in(B, stage), ep,
+                                          (item - st[b]) * 4 + (threadIdx.x >> 6));
+    }
+}
+
+// Persistent batched eta / zeta sweep of one RK stage; the last direction
+// applies the RK3 update.
+template <int DIM, int DIR, int RECON, int Y, int PREC>
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_wg(BTab t, SchemeK sk, int stage) {
+    __shared__ double fl[3][4][DIM + 2][64];
+    constexpr int KIND = DIR == 1 ? BK_ETA : BK_ZETA;
+    constexpr int MODE = DIR == DIM - 1 ? EPI_LAST_RK : EPI_MID;
+    const int nblk = *t.nblk;
+    const long* st = t.start + KIND * (t.cap + 1);
+    const long total = st[nblk];
+    for (long item = blockIdx.x; item < total; item += gridDim.x) {
+        const int b = find_block(st, nblk, item);
+        const BBlock& B = t.blk[b];
+        const EpiK ep = stage_epi(B, stage, MODE, DIM);
+        sweep_wg_item<DIM, DIR, RECON, Y, PREC>(B.G, sk, B.met, stage_in(B, stage), ep, B.S[DIR],
+                                                item - st[b], fl);
+        __syncthreads();  // the next item rewrites the LDS ring
     }
 }
 
@@ -268,7 +400,16 @@ using faceflux_fn = hipError_t (*)(const GeoK&, const SchemeK&, const double*, c
 // one direction sweep of the given instantiation with epilogue `ep`
 using dir_fn = hipError_t (*)(const SweepArgs&, int dir, const EpiK& ep, hipStream_t);
 
+// one RK stage of a batch part: the xi, eta (and zeta) persistent sweeps,
+// grid[k] workgroups for sweep kind k; only >= 0 launches that kind alone
+using batch_stage_fn = hipError_t (*)(const BTab&, const SchemeK&, int stage, const int grid[3],
+                                      int only, hipStream_t);
+// resident workgroups per CU of the batched sweep of kind k
+using batch_occ_fn = int (*)(int kind);
+
 stage_fn get_stage_fn(int ndim, int recon, int Y, int prec);
+batch_stage_fn get_batch_stage_fn(int ndim, int recon, int Y, int prec);
+batch_occ_fn get_batch_occ_fn(int ndim, int recon, int Y, int prec);
 faceflux_fn get_faceflux_fn(int ndim, int dir, int recon, int Y, int prec);
 dir_fn get_dir_fn(int ndim, int recon, int Y, int prec);
 

@@ -140,13 +140,11 @@ __global__ __launch_bounds__(256) void k_periodic_fill(GeoK G, int ndim, int nva
 
 // Copies the ghost layers of the frozen axes (nodes outside the interior
 // along a frozen axis, interior along the others: the only ghost nodes the
-// sweeps read) of src into dst1 and dst2.  The RK3 driver uses it to give
-// its stage arrays the caller's boundary values.
-__global__ __launch_bounds__(256) void k_frozen_ghosts(GeoK G, int ndim, int nvar,
-                                                       const double* __restrict__ src,
-                                                       double* __restrict__ dst1,
-                                                       double* __restrict__ dst2) {
-    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+// sweeps read) of src into dst1 and dst2, for the node with flat index tid.
+// The RK3 drivers use it to give their stage registers the caller's boundary
+// values.
+__device__ __forceinline__ void frozen_ghost_node(const GeoK& G, int ndim, int nvar, const double* src,
+                                                  double* dst1, double* dst2, long tid) {
     if (tid >= G.vol) return;
     int N[3];
     N[0] = G.n[0] + 2 * G.g;
@@ -168,6 +166,25 @@ __global__ __launch_bounds__(256) void k_frozen_ghosts(GeoK G, int ndim, int nva
         const double x = src[v * G.vol + tid];
         dst1[v * G.vol + tid] = x;
         dst2[v * G.vol + tid] = x;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_frozen_ghosts(GeoK G, int ndim, int nvar,
+                                                       const double* __restrict__ src,
+                                                       double* __restrict__ dst1,
+                                                       double* __restrict__ dst2) {
+    frozen_ghost_node(G, ndim, nvar, src, dst1, dst2, (long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Batched form: one item = 256 nodes of one block's ghost-copy range.
+__global__ __launch_bounds__(256) void kb_frozen_ghosts(BTab t, int ndim) {
+    const int nblk = *t.nblk;
+    const long* st = t.start + BK_GHOST * (t.cap + 1);
+    const long total = st[nblk];
+    for (long item = blockIdx.x; item < total; item += gridDim.x) {
+        const int b = find_block(st, nblk, item);
+        const BBlock& B = t.blk[b];
+        frozen_ghost_node(B.G, ndim, ndim + 2, B.q, B.A, B.B, (item - st[b]) * 256 + threadIdx.x);
     }
 }
 

@@ -22,7 +22,8 @@ FP_BC_PERIODIC, FP_BC_FROZEN = 0, 1
 
 EXPORTS = ["fp_state_bytes", "fp_metric_bytes", "fp_coord_bytes", "fp_work_bytes", "fp_metrics",
            "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve", "fp_max_dt",
-           "fp_check_state", "fp_release_cache", "fp_last_error"]
+           "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step", "fp_batch_solve",
+           "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error"]
 
 
 class FPError(RuntimeError):
@@ -39,6 +40,11 @@ class FPGrid(C.Structure):
 class FPScheme(C.Structure):
     _fields_ = [("recon", C.c_int32), ("metric_order", C.c_int32), ("reformulated", C.c_int32),
                 ("precision", C.c_int32), ("gamma", C.c_double), ("weno_eps", C.c_double)]
+
+
+class FPBlock(C.Structure):
+    _fields_ = [("grid", FPGrid), ("met", C.c_void_p), ("q", C.c_void_p), ("work", C.c_void_p),
+                ("dt", C.c_double)]
 
 
 _lib = None
@@ -65,11 +71,22 @@ def lib():
         L.fp_solve.argtypes = [gp, sp, dp, dp, dp, C.c_double, C.c_int64, vp]
         L.fp_max_dt.argtypes = [gp, sp, dp, dp, C.c_double, dp, vp]
         L.fp_check_state.argtypes = [gp, sp, dp, dp, vp]
+        bp = C.c_void_p
+        L.fp_batch_create.argtypes = [sp, C.c_int32, C.POINTER(C.c_void_p)]
+        L.fp_batch_set.argtypes = [bp, C.POINTER(FPBlock), C.c_int32, vp]
+        L.fp_batch_rk3_step.argtypes = [bp, vp]
+        L.fp_batch_solve.argtypes = [bp, C.c_int64, vp]
+        L.fp_batch_autotune.argtypes = [bp, C.POINTER(C.c_int32), vp]
+        L.fp_batch_profile_step.argtypes = [bp, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32,
+                                            C.POINTER(C.c_int32), vp]
+        L.fp_batch_destroy.argtypes = [bp]
+        L.fp_batch_destroy.restype = None
         L.fp_release_cache.argtypes = []
         L.fp_release_cache.restype = None
         L.fp_last_error.restype = C.c_char_p
         for name in ("fp_metrics", "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve",
-                     "fp_max_dt", "fp_check_state"):
+                     "fp_max_dt", "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step",
+                     "fp_batch_solve", "fp_batch_autotune", "fp_batch_profile_step"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -254,6 +271,67 @@ def check_state(grid: Grid, scheme: Scheme, q, flag=None) -> torch.Tensor:
     _check(lib().fp_check_state(C.byref(g), C.byref(s), _dev(q, state_bytes(grid), "q"),
                                 C.c_void_p(flag.data_ptr()), _stream()))
     return flag
+
+
+class Batch:
+    """Many independent blocks advanced by shared launches (fp_batch_*).
+
+    set() takes (grid, met, q, work, dt) tuples of float64 GPU tensors; the
+    tensors are kept referenced here until the next set() or close(), so the
+    device memory the batch's work list points to stays alive."""
+
+    def __init__(self, scheme: Scheme, max_blocks: int):
+        self._sc = scheme.c()
+        h = C.c_void_p()
+        _check(lib().fp_batch_create(C.byref(self._sc), int(max_blocks), C.byref(h)))
+        self._h = h
+        self._keep = []
+        self.max_blocks = int(max_blocks)
+
+    def set(self, blocks):
+        arr = (FPBlock * max(1, len(blocks)))()
+        keep = []
+        for i, (grid, met, q, work, dt) in enumerate(blocks):
+            arr[i].grid = grid.c()
+            arr[i].met = _dev(met, metric_bytes(grid), "met")
+            arr[i].q = _dev(q, state_bytes(grid), "q")
+            arr[i].work = _dev(work, work_bytes(grid), "work")
+            arr[i].dt = float(dt)
+            keep.append((met, q, work))
+        _check(lib().fp_batch_set(self._h, arr, len(blocks), _stream()))
+        self._keep = keep
+
+    def rk3_step(self):
+        _check(lib().fp_batch_rk3_step(self._h, _stream()))
+
+    def solve(self, nsteps: int):
+        _check(lib().fp_batch_solve(self._h, int(nsteps), _stream()))
+
+    def autotune(self) -> int:
+        seg = C.c_int32(0)
+        _check(lib().fp_batch_autotune(self._h, C.byref(seg), _stream()))
+        return int(seg.value)
+
+    def profile_step(self):
+        """One RK3 step with per-launch HIP-event timing: [(ndim, kind, ms)]
+        in launch order, kind 0/1/2 = xi/eta/zeta sweep, 3 = ghost copy."""
+        ms = (C.c_float * 32)()
+        kinds = (C.c_int32 * 32)()
+        n = C.c_int32(0)
+        _check(lib().fp_batch_profile_step(self._h, ms, kinds, 32, C.byref(n), _stream()))
+        return [(kinds[i] // 16, kinds[i] % 16, float(ms[i])) for i in range(n.value)]
+
+    def close(self):
+        if self._h:
+            lib().fp_batch_destroy(self._h)
+            self._h = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release_cache() -> None:

@@ -71,3 +71,18 @@ def test_null_arrays_rejected():
     assert L.fp_residual(C.byref(g), C.byref(s), None, None, None, None) == fp.FP_EINVAL
     assert L.fp_rk3_step(C.byref(g), C.byref(s), None, None, None, 0.1, None) == fp.FP_EINVAL
     assert L.fp_metrics(C.byref(g), 6, None, None, None) == fp.FP_EINVAL
+
+
+def test_batch_arguments_rejected_without_a_device():
+    L = fp.lib()
+    sc = fp.Scheme().c()
+    h = C.c_void_p()
+    assert L.fp_batch_create(C.byref(sc), 0, C.byref(h)) == fp.FP_EINVAL
+    assert L.fp_batch_create(C.byref(sc), 1, None) == fp.FP_EINVAL
+    bad = fp.Scheme(metric_order=5).c()
+    assert L.fp_batch_create(C.byref(bad), 4, C.byref(h)) == fp.FP_EUNSUPPORTED
+    assert L.fp_batch_set(None, None, 0, None) == fp.FP_EINVAL
+    assert L.fp_batch_rk3_step(None, None) == fp.FP_EINVAL
+    assert L.fp_batch_solve(None, 1, None) == fp.FP_EINVAL
+    assert L.fp_batch_autotune(None, None, None) == fp.FP_EINVAL
+    L.fp_batch_destroy(None)

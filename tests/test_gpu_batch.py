@@ -1,0 +1,211 @@
+"""Batched multi-block RK3 (fp_batch_*) on the GPU.
+
+Every block of a batch must come out bitwise equal to the same block
+advanced alone by fp_rk3_step (same kernels' arithmetic, only the work
+distribution differs), whatever the mix of 2D/3D, periodic/frozen blocks,
+after a change of the block set, through the captured step graph, and after
+the autotuner changes the tile shape.  The single-block path is held to the
+FP64 oracle by the parity tests; one block here is also checked against the
+oracle directly.  At the full 48-block O-grid workload the batch must also
+keep the uniform Mach-3 free stream to round-off in FP64 and FP32-mixed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2101_05886_amd import fp
+from paper_2101_05886_amd import inputs as I
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "these tests need the MI355X"
+    fp.lib()
+    yield
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def mixed_cases():
+    """uneven blocks: 3D periodic and frozen, 2D periodic"""
+    return [G.periodic_case(3, (20, 17, 13), 6, state="noisy", seed=11),
+            G.frozen_case((40, 24, 16), 6, perturb=0.05, seed=12),
+            G.periodic_case(2, (50, 37), 6, state="noisy", seed=13),
+            G.frozen_case((33, 20, 18), 6, perturb=0.03, seed=14),
+            G.periodic_case(3, (70, 9, 11), 6, state="vortex", seed=15),
+            G.periodic_case(2, (19, 64), 6, state="vortex", seed=16)]
+
+
+class Block:
+    def __init__(self, case, scheme, cfl=0.5):
+        self.case = case
+        self.grid = fp.Grid(case["ndim"], case["n"], case["g"], bc=case["bc"])
+        self.met = fp.metrics(self.grid, case["Y"], dev(case["xyz"]))
+        self.q0 = dev(case["q"])
+        self.q = self.q0.clone()
+        self.work = torch.zeros(self.grid.work_shape(), dtype=torch.float64, device="cuda")
+        self.dt = float(fp.max_dt(self.grid, scheme, self.met, self.q0, cfl).item())
+
+    def entry(self):
+        return (self.grid, self.met, self.q, self.work, self.dt)
+
+    def alone(self, scheme, steps):
+        q = self.q0.clone()
+        w = torch.zeros_like(self.work)
+        for _ in range(steps):
+            fp.rk3_step(self.grid, scheme, self.met, q, w, self.dt)
+        return q
+
+
+SCHEMES = [("weno5", "fp64"), ("linup5", "fp64"), ("weno5", "mixed")]
+
+
+@pytest.mark.parametrize("recon,prec", SCHEMES)
+def test_batch_step_bitwise_equals_blocks_alone(recon, prec):
+    sc = fp.Scheme(recon, 6, True, precision=prec)
+    blocks = [Block(c, sc) for c in mixed_cases()]
+    b = fp.Batch(sc, 16)
+    b.set([k.entry() for k in blocks])
+    b.rk3_step()
+    torch.cuda.synchronize()
+    for i, k in enumerate(blocks):
+        ref = k.alone(sc, 1)
+        assert torch.equal(k.q, ref), f"block {i}: batched step differs from the block alone"
+    b.close()
+
+
+def test_batch_block_matches_oracle():
+    sc = fp.Scheme("weno5", 6, True)
+    cases = mixed_cases()
+    blocks = [Block(c, sc) for c in cases]
+    b = fp.Batch(sc, 8)
+    b.set([k.entry() for k in blocks])
+    b.rk3_step()
+    torch.cuda.synchronize()
+    for i in (1, 2):  # a frozen 3D block and a periodic 2D block
+        c, k = cases[i], blocks[i]
+        og = O.Grid(c["ndim"], c["n"], c["g"], bc=c["bc"])
+        met = k.met.cpu().numpy()
+        ref = O.rk3_step(og, O.Scheme("weno5", 6, True), met, c["q"], k.dt)
+        got = k.q.cpu().numpy()
+        sl = (slice(None),) + (slice(c["g"], -c["g"]),) * c["ndim"]
+        for v in range(got.shape[0]):
+            err = np.abs(got[sl][v] - ref[sl][v]).max() / np.abs(ref[sl][v]).max()
+            assert err <= 1e-12, f"block {i} variable {v}: {err:.3e}"
+    b.close()
+
+
+def test_batch_graph_survives_set_changes():
+    sc = fp.Scheme("weno5", 6, True)
+    blocks = [Block(c, sc) for c in mixed_cases()]
+    b = fp.Batch(sc, 8)
+    # all blocks, graph replay of 3 steps
+    b.set([k.entry() for k in blocks])
+    b.solve(3)
+    torch.cuda.synchronize()
+    for i, k in enumerate(blocks):
+        assert torch.equal(k.q, k.alone(sc, 3)), f"block {i} after 3 graph steps"
+    # a different subset (3D only, then 2D only, then all again): the work
+    # list changes under the captured graphs
+    subsets = [[0, 1, 4], [2, 5], [5, 3, 0, 2]]
+    for sub in subsets:
+        for i in sub:
+            blocks[i].q.copy_(blocks[i].q0)
+            blocks[i].dt *= 0.9
+        b.set([blocks[i].entry() for i in sub])
+        b.solve(2)
+        torch.cuda.synchronize()
+        for i in sub:
+            assert torch.equal(blocks[i].q, blocks[i].alone(sc, 2)), f"subset {sub}: block {i}"
+    b.set([])
+    b.solve(1)  # an empty batch is a no-op
+    b.close()
+
+
+def test_batch_autotune_keeps_results():
+    sc = fp.Scheme("linup5", 6, True)
+    blocks = [Block(c, sc) for c in mixed_cases()]
+    b = fp.Batch(sc, 8)
+    b.set([k.entry() for k in blocks])
+    seg = b.autotune()
+    assert seg in (15, 23, 31, 47, 63, 95, 127)
+    for k in blocks:
+        assert torch.equal(k.q, k.q0), "the autotuner must not touch q"
+    b.solve(2)
+    torch.cuda.synchronize()
+    for i, k in enumerate(blocks):
+        assert torch.equal(k.q, k.alone(sc, 2)), f"block {i} after autotune"
+    b.close()
+
+
+def test_batch_rejects_bad_blocks():
+    sc = fp.Scheme("weno5", 6, True)
+    k = Block(G.periodic_case(3, (12, 12, 12), 6), sc)
+    b = fp.Batch(sc, 2)
+    with pytest.raises(fp.FPError):
+        b.set([k.entry()] * 3)  # more than max_blocks
+    bad = list(k.entry())
+    bad[4] = -1.0
+    with pytest.raises(fp.FPError):
+        b.set([tuple(bad)])
+    g2 = fp.Grid(3, (12, 12, 12), 2)  # ghost too small for 6th-order metrics
+    with pytest.raises(fp.FPError):
+        b.set([(g2, k.met, k.q, k.work, k.dt)])
+    b.close()
+
+
+def c4_blocks(scheme, perturb=False):
+    out = []
+    for i, spec in enumerate(I.multiblock_specs(48, seed=4)):
+        g, Y = 3, 6
+        xyz = I.ogrid_sector_block(spec.n, g, Y, spec.sector, spec.skew_deg, spec.rotation)
+        q = I.uniform_state(3, spec.n, g, G.GAMMA, I.mach_velocity(3.0, [1.0, 0.0, 0.0]), 1.0)
+        out.append(Block(dict(ndim=3, n=list(spec.n), g=g, Y=Y, bc=[1, 1, 1], xyz=xyz, q=q), scheme))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c4_free_stream_and_bitwise(prec):
+    sc = fp.Scheme("weno5", 6, True, precision=prec)
+    blocks = c4_blocks(sc)
+    nodes = sum(int(np.prod(k.grid.n)) for k in blocks)
+    print(f"C4: 48 O-grid blocks, {nodes} nodes, {prec}", flush=True)
+    b = fp.Batch(sc, 48)
+    b.set([k.entry() for k in blocks])
+    b.solve(5)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k in blocks:
+        g = k.grid.ghost
+        d = (k.q - k.q0)[:, g:-g, g:-g, g:-g].abs().amax(dim=(1, 2, 3))
+        # per variable, relative to its free-stream size; the momentum
+        # components (zero for the ones normal to the flow) to rho |u|
+        scale = k.q0[:, g:-g, g:-g, g:-g].abs().amax(dim=(1, 2, 3))
+        scale[1:4] = scale[1:4].max()
+        worst = max(worst, float((d / scale).max()))
+    print(f"C4 free-stream deviation after 5 steps: {worst:.3e}", flush=True)
+    assert worst < 1e-13
+    for i in (0, 17, 47):
+        assert torch.equal(blocks[i].q, blocks[i].alone(sc, 5)), f"block {i}"
+    b.close()
+
+
+def test_batch_profile_step_is_a_step():
+    sc = fp.Scheme("weno5", 6, True, precision="mixed")
+    blocks = [Block(c, sc) for c in mixed_cases()]
+    b = fp.Batch(sc, 8)
+    b.set([k.entry() for k in blocks])
+    prof = b.profile_step()
+    # 2D part: ghost copy + 3 stages x 2 sweeps; 3D part: ghost copy + 3 x 3
+    assert [(d, k) for d, k, _ in prof] == ([(2, 3)] + [(2, k) for _ in range(3) for k in (0, 1)]
+                                            + [(3, 3)] + [(3, k) for _ in range(3) for k in (0, 1, 2)])
+    assert all(t > 0.0 for _, _, t in prof)
+    for i, k in enumerate(blocks):
+        assert torch.equal(k.q, k.alone(sc, 1)), f"block {i}"
+    b.close()
