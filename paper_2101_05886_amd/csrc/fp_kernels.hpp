@@ -48,6 +48,19 @@ struct EpiK {
     double dt, a, b;
 };
 
+// Buffer access to one variable array: the resource (base, size) is
+// wave-uniform and lives in scalar registers, every lane supplies a 32-bit
+// byte offset, so no 64-bit vector address arithmetic is spent per access.
+// Reads past `elems` return 0 by the hardware's range check.  A variable array must stay below 4 GiB (checked
+// by the host: at most 2^29 nodes per block, ghosts included).
+#define FP_BUF_FLAGS 0x00020000
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const double* base, long elems) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(elems * 8), FP_BUF_FLAGS);
+}
+__device__ __forceinline__ double ldb(const double* base, long elems, unsigned byteoff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(buf(base, elems), byteoff, 0, 0));
+}
+
 template <int NV>
 __device__ __forceinline__ void epilogue(const EpiK& ep, long vol, long off, const double (&d)[NV]) {
     if (ep.mode == EPI_FIRST) {
@@ -70,14 +83,6 @@ __device__ __forceinline__ void epilogue(const EpiK& ep, long vol, long off, con
             ep.out[o] = ep.stage0 ? u : ep.a * ep.qn[o] + ep.b * u;
         }
     }
-}
-
-// Load at a 32-bit byte offset from a wave-uniform base: the base pointers
-// (array + variable * vol) are computed in scalar registers and every lane
-// adds one 32-bit offset, so no 64-bit vector address arithmetic is spent per
-// load.  A variable array must stay below 4 GiB (checked by the host).
-__device__ __forceinline__ double ldg(const double* base, unsigned byteoff) {
-    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byteoff);
 }
 
 // Reads the stencil of face i+1/2 of one grid line along axis DIR: slot r
@@ -120,10 +125,10 @@ struct LineLoader {
         const unsigned off = (lb + (unsigned)(tt * sd)) * 8u;
         const unsigned moff = (lb + (unsigned)(t * sd)) * 8u;
 #pragma unroll
-        for (int v = 0; v < DIM + 2; ++v) qv[v] = ldg(q + v * vol, off);
-        V = ldg(met + (NMET - 1) * vol, moff);
+        for (int v = 0; v < DIM + 2; ++v) qv[v] = ldb(q + v * vol, vol, off);
+        V = ldb(met + (NMET - 1) * vol, vol, moff);
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) s[c] = ldg(met + (DIR * DIM + c) * vol, moff);
+        for (int c = 0; c < DIM; ++c) s[c] = ldb(met + (DIR * DIM + c) * vol, vol, moff);
     }
 };
 
@@ -168,22 +173,75 @@ __device__ __forceinline__ void sweep_x_wave(const GeoK& G, const SchemeK& sk,
 // Waves of the xi sweep of one block (four per workgroup of 256 threads).
 inline long sweep_x_waves(const int n[3]) { return ((long)(n[0] + 1) * n[1] * n[2] + 62) / 63; }
 
+// LDS of an eta / zeta sweep workgroup: a ring of stencil rows (the q, 1/J
+// and s_DIR values of the workgroup's 64 lines at one node index along
+// DIR) and a double buffer of the four face fluxes of an iteration.
+template <int DIM, int Y>
+struct WgLds {
+    static constexpr int NV = DIM + 2;
+    static constexpr int NS = 2 * DIM + 3;   // values per node: q, 1/J, s_DIR
+    static constexpr int LO = Y == 8 ? 3 : 2;  // rows below face i+1/2 read by it: i-LO+1 .. i
+    static constexpr int HI = Y == 8 ? 4 : 3;  // rows above: i+1 .. i+HI
+    static constexpr int WIN = 4 + LO + HI;    // rows read by the four faces of an iteration
+    static constexpr int RING = WIN + 4;       // plus the four rows prefetched for the next
+    double ring[RING][NS][64];
+    double flux[2][4][NV][64];
+};
+
+// Stencil reads of face i+1/2 from the LDS ring: slot r (node i-3+r) is ring
+// row (b0 + r) mod RING.
+template <int DIM, int Y>
+struct LdsLoader {
+    using W = WgLds<DIM, Y>;
+    const W* L;
+    unsigned la;  // byte offset of this lane in a ring row
+    int b0;       // ring row of slot 0, in [0, RING)
+
+    __device__ __forceinline__ LdsLoader after(double dep) const {
+        LdsLoader c = *this;
+        asm volatile("" : "+v"(c.la) : "v"(dep));
+        return c;
+    }
+
+    __device__ __forceinline__ void slot(int r, double (&qv)[DIM + 2], double& V,
+                                         double (&s)[DIM]) const {
+        int idx = b0 + r;
+        idx = idx >= W::RING ? idx - W::RING : idx;
+        const char* row = reinterpret_cast<const char*>(&L->ring[idx][0][0]) + la;
+#pragma unroll
+        for (int v = 0; v < DIM + 2; ++v) qv[v] = *reinterpret_cast<const double*>(row + v * 512);
+        V = *reinterpret_cast<const double*>(row + (DIM + 2) * 512);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) s[c] = *reinterpret_cast<const double*>(row + (DIM + 3 + c) * 512);
+    }
+};
+
+// One dword per lane from a variable array into LDS (global-to-LDS DMA: no
+// registers hold the data; completion is tracked by the wave's vmcnt).
+// Lane l writes the dword at lds + 4 l.
+__device__ __forceinline__ void dma_dword(const double* var, void* lds, unsigned byteoff) {
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(var) + byteoff,
+                                     (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+
 // eta / zeta sweeps: a workgroup of four waves owns 64 grid lines along DIR
-// (consecutive in the flattened (i, other) index, so loads are coalesced)
-// and one segment [k0, k1) of S nodes of them; work item `item` of a block
-// is (line block = item % lblocks, segment = item / lblocks).  Per iteration
-// wave w evaluates the face f+1/2, f = k0 - 1 + 4 it + w, on its 64 lines;
-// the fluxes go to the LDS ring `fl` (three rotating buffers of four rows,
-// so one barrier per iteration suffices) and wave w then forms node f's
-// difference F'_{f+1/2} - F'_{f-1/2}.  Every thread of the workgroup runs
-// the same number of iterations (no early exit before a barrier).  A caller
-// that reuses `fl` for another item must synchronise the workgroup first.
+// (consecutive in the flattened (i, other) index, so row loads are
+// coalesced) and one segment [k0, k1) of S nodes of them; work item `item`
+// of a block is (line block = item % lblocks, segment = item / lblocks).
+// The stencil rows are staged in an LDS ring by global-to-LDS DMA, one row
+// per wave per iteration, prefetched one iteration ahead.  Per iteration
+// wave w evaluates the face f+1/2, f = k0 - 1 + 4 it + w, on its 64 lines
+// from the ring, the fluxes go to LDS and wave w forms node f's difference
+// F'_{f+1/2} - F'_{f-1/2}.  Every thread of the workgroup runs the same
+// iterations and barriers.  A caller that reuses `L` for another item must
+// synchronise the workgroup first.
 template <int DIM, int DIR, int RECON, int Y, int PREC>
 __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
                                               const double* __restrict__ met, const double* qs,
-                                              const EpiK& ep, int S, long item,
-                                              double (*fl)[4][DIM + 2][64]) {
+                                              const EpiK& ep, int S, long item, WgLds<DIM, Y>& L) {
+    using W = WgLds<DIM, Y>;
     constexpr int NV = DIM + 2;
+    constexpr int NMET = DIM == 3 ? 10 : 5;
     constexpr int OTH = DIR == 1 ? 2 : 1;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -196,31 +254,70 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
     const int i = lane_ok ? (int)(line % G.n[0]) : 0;
     const int o = lane_ok ? (int)(line / G.n[0]) : 0;
     const long lb = G.base + i + (long)o * G.sd[OTH];
+    // DMA: lane l moves dword (l & 1) of line 32 h + l / 2 (h = 0, 1) of the
+    // block; lines past the end repeat the last one
+    unsigned loff[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        long ln = lineblk * 64 + 32 * h + (lane >> 1);
+        ln = ln < nlines ? ln : nlines - 1;
+        const long off = G.base + ln % G.n[0] + (ln / G.n[0]) * G.sd[OTH];
+        loff[h] = (unsigned)off * 8u + (unsigned)(lane & 1) * 4u;
+    }
     const int nd = G.n[DIR];
+    const int per = G.bc[DIR] == 0;
+    const int sdD = (int)G.sd[DIR];
+    const long vol = G.vol;
     const int k0 = seg * S;
     const int k1 = min(k0 + S, nd);
     const int iters = (k1 - k0 + 1 + 3) / 4;  // faces k0-1/2 .. k1-1/2
+    const int tb = k0 - 1 - W::LO;            // node index of ring row 0
+    const int tmax = k1 - 1 + W::HI;          // last row any needed face reads
+    auto load_row = [&](int t) {
+        if (t > tmax) return;
+        const int slot = (t - tb) % W::RING;
+        int tt = t;
+        if (per) tt = t < 0 ? t + nd : (t >= nd ? t - nd : t);
+        const unsigned qo = (unsigned)(tt * sdD) * 8u, mo = (unsigned)(t * sdD) * 8u;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) dma_dword(qs + v * vol, &L.ring[slot][v][32 * h], loff[h] + qo);
+            dma_dword(met + (NMET - 1) * vol, &L.ring[slot][NV][32 * h], loff[h] + mo);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+                dma_dword(met + (DIR * DIM + c) * vol, &L.ring[slot][NV + 1 + c][32 * h], loff[h] + mo);
+        }
+    };
+    for (int r = w; r < W::WIN; r += 4) load_row(tb + r);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     for (int it = 0; it < iters; ++it) {
         const int f = k0 - 1 + 4 * it + w;
-        const int buf = it % 3;
+        if (it + 1 < iters) load_row(tb + W::WIN + 4 * it + w);  // a row of the next iteration
         double F[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = 0.0;
         if (lane_ok && f < k1) {
-            const LineLoader<DIM, DIR> ld(G, met, qs, lb, f);
+            LdsLoader<DIM, Y> ld;
+            ld.L = &L;
+            ld.la = (unsigned)lane * 8u;
+            ld.b0 = (f - 3 - tb + W::RING) % W::RING;
             face_flux<DIM, RECON, Y, char_t<PREC>>(ld, sk, F);
         }
+        const int buf = it & 1;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) fl[buf][w][v][lane] = F[v];
+        for (int v = 0; v < NV; ++v) L.flux[buf][w][v][lane] = F[v];
         __syncthreads();
         if (lane_ok && f >= k0 && f < k1) {
-            const int pb = w > 0 ? buf : (it + 2) % 3;
-            const int pr = w > 0 ? w - 1 : 3;
+            const double* prev = w > 0 ? &L.flux[buf][w - 1][0][0] : &L.flux[buf ^ 1][3][0][0];
             double d[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) d[v] = F[v] - fl[pb][pr][v][lane];
+            for (int v = 0; v < NV; ++v) d[v] = F[v] - prev[v * 64 + lane];
             epilogue<NV>(ep, G.vol, lb + (long)f * G.sd[DIR], d);
         }
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's row DMA has landed
+        __syncthreads();                // every row of the next iteration is in LDS
     }
 }
 
@@ -242,8 +339,8 @@ template <int DIM, int DIR, int RECON, int Y, int PREC>
 __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK sk,
                                                                 const double* __restrict__ met,
                                                                 const double* qs, EpiK ep, int S) {
-    __shared__ double fl[3][4][DIM + 2][64];
-    sweep_wg_item<DIM, DIR, RECON, Y, PREC>(G, sk, met, qs, ep, S, blockIdx.x, fl);
+    __shared__ WgLds<DIM, Y> lds;
+    sweep_wg_item<DIM, DIR, RECON, Y, PREC>(G, sk, met, qs, ep, S, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -336,7 +433,7 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(BTab t, SchemeK 
 // applies the RK3 update.
 template <int DIM, int DIR, int RECON, int Y, int PREC>
 __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_wg(BTab t, SchemeK sk, int stage) {
-    __shared__ double fl[3][4][DIM + 2][64];
+    __shared__ WgLds<DIM, Y> lds;
     constexpr int KIND = DIR == 1 ? BK_ETA : BK_ZETA;
     constexpr int MODE = DIR == DIM - 1 ? EPI_LAST_RK : EPI_MID;
     const int nblk = *t.nblk;
@@ -347,7 +444,7 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_wg(BTab t, SchemeK
         const BBlock& B = t.blk[b];
         const EpiK ep = stage_epi(B, stage, MODE, DIM);
         sweep_wg_item<DIM, DIR, RECON, Y, PREC>(B.G, sk, B.met, stage_in(B, stage), ep, B.S[DIR],
-                                                item - st[b], fl);
+                                                item - st[b], lds);
         __syncthreads();  // the next item rewrites the LDS ring
     }
 }
