@@ -31,12 +31,26 @@ void launch_wg(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
                        dim3(256), 0, s, a.G, a.sk, a.met, a.qs, ep, a.S[DIR]);
 }
 
+// resident workgroups of a kernel on the current device (queried once)
+template <class K>
+int resident(K* kern) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 512;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 512;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kern), 256, 0) !=
+            hipSuccess ||
+        per < 1)
+        per = 1;
+    return per * cus;
+}
+
 template <int DIM, int Y>
 void launch_x(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
-    const long faces = (long)(a.G.n[0] + 1) * a.G.n[1] * a.G.n[2];
-    const long waves = (faces + 62) / 63;
-    hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, a.G,
-                       a.sk, a.met, a.qs, ep);
+    static const int res = resident(&k_sweep_x<DIM, R, Y, P>);
+    const long items = sweep_x_items(a.G.n);
+    const long wgs = (items + 3) / 4;
+    hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3((unsigned)(wgs < res ? wgs : res)), dim3(256), 0, s,
+                       a.G, a.sk, a.met, a.qs, ep);
 }
 
 template <int DIM, int Y>

@@ -135,43 +135,166 @@ struct LineLoader {
 template <int PREC>
 using char_t = typename std::conditional<PREC == 1, float, double>::type;
 
-// xi sweep: 64 lanes evaluate 64 consecutive faces of the flattened face index
-// (faces of consecutive xi-lines one after another); waves overlap by one face
-// so that every lane but the first takes its left neighbour's flux by a lane
-// shift and forms the flux difference of its node.  `wave` numbers the waves
-// of one block; all 64 lanes must call this (the lane shift).
-template <int DIM, int RECON, int Y, int PREC>
-__device__ __forceinline__ void sweep_x_wave(const GeoK& G, const SchemeK& sk,
-                                             const double* __restrict__ met, const double* qs,
-                                             const EpiK& ep, long wave) {
+// One dword per lane from a variable array into LDS (global-to-LDS DMA: no
+// registers hold the data; completion is tracked by the wave's vmcnt).
+// Lane l writes the dword at lds + 4 l.
+__device__ __forceinline__ void dma_dword(const double* var, void* lds, unsigned byteoff) {
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(var) + byteoff,
+                                     (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// xi sweep
+// ---------------------------------------------------------------------------
+// The faces of all xi-lines of a block are numbered flat, F = L (n0+1) + f
+// (line L, face f-1/2 of it).  A wave item takes W consecutive faces,
+// F = (W-1) j + l for lane l < W, so consecutive items overlap by one face:
+// lane l > 0 takes its left neighbour's flux by a lane shift and forms the
+// flux difference of its node.  The stencil nodes of the item are staged in
+// the wave's own LDS buffer by global-to-LDS DMA, indexed by the extended
+// flat index e = L (n0+8) + x + 4 (line L with four extra nodes on each side,
+// x = -4 .. n0+3): slot r (node f-4+r) of face F is entry e(F) + r with
+// e(F) = L (n0+8) + f.  A window of W faces spans W + 7 (lines touched)
+// entries; W is the largest width (at most 64) that fits XE entries.
+template <int DIM>
+struct XLds {
+    static constexpr int NE = 128;          // staged entries per buffer
+    static constexpr int NS = 2 * DIM + 3;  // q, 1/J, s_xi
+    double b[2][NS][NE];                    // double buffer: current item, next item
+};
+
+__device__ __host__ __forceinline__ int x_window(int n0) {
+    int W = 64;
+    while (W > 2 && W + 7 * ((W + n0) / (n0 + 1) + 1) > XLds<3>::NE) --W;
+    return W;
+}
+
+// wave items of the xi sweep of one block
+__device__ __host__ __forceinline__ long sweep_x_items(const int n[3]) {
+    const long total = (long)(n[0] + 1) * n[1] * n[2];
+    const int W = x_window(n[0]);
+    return (total - 1 + W - 2) / (W - 1);
+}
+
+// Stage item j's stencil entries into buf (all 64 lanes; asynchronous).
+template <int DIM>
+__device__ __forceinline__ void x_stage(const GeoK& G, const double* __restrict__ met, const double* qs,
+                                        long j, int W, double (*buf)[XLds<DIM>::NE]) {
     constexpr int NV = DIM + 2;
-    const int lane = threadIdx.x & 63;
-    const long F = wave * 63 + lane;
-    const int nf = G.n[0] + 1;
-    const long total = (long)nf * G.n[1] * G.n[2];
-    const bool active = F < total;
+    constexpr int NMET = DIM == 3 ? 10 : 5;
+    const unsigned lane = threadIdx.x & 63;
+    const unsigned n0 = (unsigned)G.n[0], nf = n0 + 1, ne = n0 + 8;
+    const unsigned nlines = (unsigned)G.n[1] * (unsigned)G.n[2];
+    const unsigned F0 = (unsigned)((W - 1) * j);
+    const unsigned L0 = F0 / nf;
+    const unsigned elo = L0 * ne + (F0 - L0 * nf);
+    const int g = G.g;
+    const int per = G.bc[0] == 0;
+#pragma unroll
+    for (int p = 0; p < XLds<DIM>::NE / 32; ++p) {
+        const unsigned e = elo + 32u * p + (lane >> 1);
+        unsigned L = e / ne;
+        int x = (int)(e - L * ne) - 4;
+        if (L >= nlines) L = nlines - 1;  // entries past the last line are never read
+        const int xm = x < -g ? -g : (x > (int)n0 - 1 + g ? (int)n0 - 1 + g : x);
+        int xq = xm;
+        if (per) {
+            xq = x < 0 ? x + (int)n0 : (x >= (int)n0 ? x - (int)n0 : x);
+            xq = xq < 0 ? 0 : (xq > (int)n0 - 1 ? (int)n0 - 1 : xq);
+        }
+        const unsigned l1 = L % (unsigned)G.n[1], l2 = L / (unsigned)G.n[1];
+        const unsigned lb = (unsigned)G.base + l1 * (unsigned)G.sd[1] + l2 * (unsigned)G.sd[2];
+        const unsigned oq = (lb + (unsigned)xq) * 8u + (lane & 1) * 4u;
+        const unsigned om = (lb + (unsigned)xm) * 8u + (lane & 1) * 4u;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dma_dword(qs + v * G.vol, &buf[v][32 * p], oq);
+        dma_dword(met + (NMET - 1) * G.vol, &buf[NV][32 * p], om);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) dma_dword(met + c * G.vol, &buf[NV + 1 + c][32 * p], om);
+    }
+}
+
+// Stencil reads of one lane's xi face from the wave's staged entries.
+template <int DIM>
+struct XLoader {
+    const double (*buf)[XLds<DIM>::NE];
+    unsigned ea;  // byte offset of entry e(F) in a variable row
+
+    __device__ __forceinline__ XLoader after(double dep) const {
+        XLoader c = *this;
+        asm volatile("" : "+v"(c.ea) : "v"(dep));
+        return c;
+    }
+
+    __device__ __forceinline__ void slot(int r, double (&qv)[DIM + 2], double& V,
+                                         double (&s)[DIM]) const {
+        constexpr int NE = XLds<DIM>::NE;
+        const char* row = reinterpret_cast<const char*>(&buf[0][0]) + ea + r * 8;
+#pragma unroll
+        for (int v = 0; v < DIM + 2; ++v) qv[v] = *reinterpret_cast<const double*>(row + v * NE * 8);
+        V = *reinterpret_cast<const double*>(row + (DIM + 2) * NE * 8);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) s[c] = *reinterpret_cast<const double*>(row + (DIM + 3 + c) * NE * 8);
+    }
+};
+
+// Faces of item j from its staged entries, the lane-shift difference and
+// the epilogue (all 64 lanes must call this: the lane shift).
+template <int DIM, int RECON, int Y, int PREC>
+__device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, const EpiK& ep, long j, int W,
+                                          const double (*buf)[XLds<DIM>::NE]) {
+    constexpr int NV = DIM + 2;
+    const unsigned lane = threadIdx.x & 63;
+    const unsigned n0 = (unsigned)G.n[0], nf = n0 + 1, ne = n0 + 8;
+    const unsigned total = nf * (unsigned)G.n[1] * (unsigned)G.n[2];
+    const unsigned F0 = (unsigned)((W - 1) * j);
+    const unsigned L0 = F0 / nf;
+    const unsigned elo = L0 * ne + (F0 - L0 * nf);
+    const unsigned F = F0 + lane;
+    const bool active = lane < (unsigned)W && F < total;
     double fl[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) fl[v] = 0.0;
-    long lb = 0;
-    int f = 0;
+    unsigned L = 0, f = 0;
     if (active) {
-        const long line = F / nf;
-        f = (int)(F - line * nf);
-        const int j = (int)(line % G.n[1]);
-        const int k = (int)(line / G.n[1]);
-        lb = G.base + (long)j * G.sd[1] + (long)k * G.sd[2];
-        const LineLoader<DIM, 0> ld(G, met, qs, lb, f - 1);
+        L = F / nf;
+        f = F - L * nf;
+        XLoader<DIM> ld;
+        ld.buf = buf;
+        ld.ea = (L * ne + f - elo) * 8u;
         face_flux<DIM, RECON, Y, char_t<PREC>>(ld, sk, fl);
     }
     double d[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) d[v] = fl[v] - __shfl_up(fl[v], 1, 64);
-    if (active && lane > 0 && f > 0) epilogue<NV>(ep, G.vol, lb + (f - 1), d);
+    if (active && lane > 0 && f > 0) {
+        const unsigned l1 = L % (unsigned)G.n[1], l2 = L / (unsigned)G.n[1];
+        const long lb = G.base + (long)l1 * G.sd[1] + (long)l2 * G.sd[2];
+        epilogue<NV>(ep, G.vol, lb + (f - 1), d);
+    }
 }
 
-// Waves of the xi sweep of one block (four per workgroup of 256 threads).
-inline long sweep_x_waves(const int n[3]) { return ((long)(n[0] + 1) * n[1] * n[2] + 62) / 63; }
+// Persistent xi sweep of one block: wave w of the grid takes items w,
+// w + (waves of the grid), ..., staging the next item while it computes.
+template <int DIM, int RECON, int Y, int PREC>
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK sk,
+                                                               const double* __restrict__ met,
+                                                               const double* qs, EpiK ep) {
+    __shared__ XLds<DIM> lds[4];
+    XLds<DIM>& L = lds[threadIdx.x >> 6];
+    const long nw = (long)gridDim.x * 4;
+    const long items = sweep_x_items(G.n);
+    const int W = x_window(G.n[0]);
+    long j = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int cur = 0;
+    if (j < items) x_stage<DIM>(G, met, qs, j, W, L.b[0]);
+    for (; j < items; j += nw, cur ^= 1) {
+        __builtin_amdgcn_s_waitcnt(0);  // item j's entries are in LDS
+        asm volatile("" ::: "memory");
+        if (j + nw < items) x_stage<DIM>(G, met, qs, j + nw, W, L.b[cur ^ 1]);
+        x_compute<DIM, RECON, Y, PREC>(G, sk, ep, j, W, L.b[cur]);
+    }
+}
 
 // LDS of an eta / zeta sweep workgroup: a ring of stencil rows (the q, 1/J
 // and s_DIR values of the workgroup's 64 lines at one node index along
@@ -215,14 +338,6 @@ struct LdsLoader {
         for (int c = 0; c < DIM; ++c) s[c] = *reinterpret_cast<const double*>(row + (DIM + 3 + c) * 512);
     }
 };
-
-// One dword per lane from a variable array into LDS (global-to-LDS DMA: no
-// registers hold the data; completion is tracked by the wave's vmcnt).
-// Lane l writes the dword at lds + 4 l.
-__device__ __forceinline__ void dma_dword(const double* var, void* lds, unsigned byteoff) {
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(var) + byteoff,
-                                     (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
-}
 
 // eta / zeta sweeps: a workgroup of four waves owns 64 grid lines along DIR
 // (consecutive in the flattened (i, other) index, so row loads are
@@ -328,13 +443,6 @@ inline long sweep_wg_items(const int n[3], int dir, int S) {
     return lblocks * ((n[dir] + S - 1) / S);
 }
 
-template <int DIM, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK sk,
-                                                               const double* __restrict__ met,
-                                                               const double* qs, EpiK ep) {
-    sweep_x_wave<DIM, RECON, Y, PREC>(G, sk, met, qs, ep, (long)blockIdx.x * 4 + (threadIdx.x >> 6));
-}
-
 template <int DIM, int DIR, int RECON, int Y, int PREC>
 __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK sk,
                                                                 const double* __restrict__ met,
@@ -412,20 +520,36 @@ __device__ __forceinline__ EpiK stage_epi(const BBlock& b, int stage, int mode, 
     return e;
 }
 
-// Persistent batched xi sweep of one RK stage: workgroup w takes items w,
-// w + gridDim.x, ... of the batch's xi items (one item = four waves of one
-// block).
+// Persistent batched xi sweep of one RK stage: wave w of the grid takes the
+// batch's wave items w, w + (waves of the grid), ..., staging the next item
+// (possibly of another block) while it computes.
 template <int DIM, int RECON, int Y, int PREC>
 __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(BTab t, SchemeK sk, int stage) {
+    __shared__ XLds<DIM> lds[4];
+    XLds<DIM>& L = lds[threadIdx.x >> 6];
     const int nblk = *t.nblk;
     const long* st = t.start + BK_X * (t.cap + 1);
     const long total = st[nblk];
-    for (long item = blockIdx.x; item < total; item += gridDim.x) {
+    const long nw = (long)gridDim.x * 4;
+    long item = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int cur = 0;
+    if (item < total) {
+        const int b = find_block(st, nblk, item);
+        const BBlock& B = t.blk[b];
+        x_stage<DIM>(B.G, B.met, stage_in(B, stage), item - st[b], x_window(B.G.n[0]), L.b[0]);
+    }
+    for (; item < total; item += nw, cur ^= 1) {
+        __builtin_amdgcn_s_waitcnt(0);
+        asm volatile("" ::: "memory");
+        if (item + nw < total) {
+            const int bn = find_block(st, nblk, item + nw);
+            const BBlock& N = t.blk[bn];
+            x_stage<DIM>(N.G, N.met, stage_in(N, stage), item + nw - st[bn], x_window(N.G.n[0]), L.b[cur ^ 1]);
+        }
         const int b = find_block(st, nblk, item);
         const BBlock& B = t.blk[b];
         const EpiK ep = stage_epi(B, stage, EPI_FIRST, DIM);
-        sweep_x_wave<DIM, RECON, Y, PREC>(B.G, sk, B.met, stage_in(B, stage), ep,
-                                          (item - st[b]) * 4 + (threadIdx.x >> 6));
+        x_compute<DIM, RECON, Y, PREC>(B.G, sk, ep, item - st[b], x_window(B.G.n[0]), L.b[cur]);
     }
 }
 
