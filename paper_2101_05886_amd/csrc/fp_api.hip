@@ -225,8 +225,9 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
     bool frozen = false;
     for (int d = 0; d < c.grid.ndim; ++d) frozen = frozen || c.grid.bc[d] == FP_BC_FROZEN;
     if (frozen) {
-        hipLaunchKernelGGL(k_frozen_ghosts, dim3((unsigned)((c.G.vol + 255) / 256)), dim3(256), 0, s,
-                           c.G, c.grid.ndim, c.grid.ndim + 2, (const double*)q, A, B);
+        const long slab = frozen_slab_nodes(c.G, c.grid.ndim);
+        hipLaunchKernelGGL(k_frozen_ghosts, dim3((unsigned)((slab + 255) / 256)), dim3(256), 0, s, c.G,
+                           c.grid.ndim, c.grid.ndim + 2, (const double*)q, A, B);
     }
     const double* metV = met + (size_t)(c.grid.ndim == 3 ? 9 : 4) * c.G.vol;
     const double* in[3] = {q, A, B};
@@ -344,7 +345,7 @@ void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, char* 
             items[BK_X] = sweep_x_items(B.G.n);
             items[BK_ETA] = sweep_wg_items(B.G.n, 1, B.S[1]);
             items[BK_ZETA] = ndim == 3 ? sweep_wg_items(B.G.n, 2, B.S[2]) : 0;
-            items[BK_GHOST] = frozen ? (B.G.vol + 255) / 256 : 0;
+            items[BK_GHOST] = frozen ? (frozen_slab_nodes(B.G, ndim) + 255) / 256 : 0;
             for (int k = 0; k < BK_KINDS; ++k) {
                 start[k * (b->cap + 1) + n] = acc[k];
                 acc[k] += items[k];

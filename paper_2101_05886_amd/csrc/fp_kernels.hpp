@@ -48,6 +48,52 @@ struct EpiK {
     double dt, a, b;
 };
 
+// The epilogue split in two, so that its loads can be issued early (before
+// the face computation) and its stores done late: epi_load reads what the
+// mode needs at node `off`, epi_store applies the same arithmetic as
+// epilogue().
+template <int NV>
+struct EpiPre {
+    double R[NV], qin[NV], qn[NV], V;
+};
+
+template <int NV>
+__device__ __forceinline__ void epi_load(const EpiK& ep, long vol, long off, EpiPre<NV>& p) {
+    if (ep.mode == EPI_FIRST) return;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) p.R[v] = ep.R[v * vol + off];
+    if (ep.mode == EPI_MID) return;
+    p.V = ep.metV[off];
+    if (ep.mode == EPI_LAST_RES) return;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) p.qin[v] = ep.qin[v * vol + off];
+    if (ep.stage0) return;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) p.qn[v] = ep.qn[v * vol + off];
+}
+
+template <int NV>
+__device__ __forceinline__ void epi_store(const EpiK& ep, long vol, long off, const EpiPre<NV>& p,
+                                          const double (&d)[NV]) {
+    if (ep.mode == EPI_FIRST) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ep.R[v * vol + off] = -d[v];
+    } else if (ep.mode == EPI_MID) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ep.R[v * vol + off] = p.R[v] - d[v];
+    } else if (ep.mode == EPI_LAST_RES) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ep.out[v * vol + off] = (p.R[v] - d[v]) / p.V;
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double k = (p.R[v] - d[v]) / p.V;
+            const double u = p.qin[v] + ep.dt * k;
+            ep.out[v * vol + off] = ep.stage0 ? u : ep.a * p.qn[v] + ep.b * u;
+        }
+    }
+}
+
 // Buffer access to one variable array: the resource (base, size) is
 // wave-uniform and lives in scalar registers, every lane supplies a 32-bit
 // byte offset, so no 64-bit vector address arithmetic is spent per access.
@@ -176,6 +222,45 @@ __device__ __host__ __forceinline__ long sweep_x_items(const int n[3]) {
     return (total - 1 + W - 2) / (W - 1);
 }
 
+// floor(k / d) for 0 <= k, d < 2^20, in single precision: exact, since
+// (k + 1/2) / d is at least 1/(2 d) away from an integer and the rounding
+// error of the product is below k / d * 2^-23.
+__device__ __forceinline__ unsigned small_div(unsigned k, float inv_d) {
+    return (unsigned)(((float)k + 0.5f) * inv_d);
+}
+
+// Line L0 + dL of the xi-lines, from the decomposition (a1, a2) of L0 over
+// (n1, n2): (l1, l2) with l1 < n1.
+__device__ __forceinline__ void line_step(unsigned a1, unsigned a2, unsigned dL, unsigned n1, unsigned& l1,
+                                          unsigned& l2) {
+    l1 = a1 + dL;
+    l2 = a2;
+    while (l1 >= n1) {
+        l1 -= n1;
+        ++l2;
+    }
+}
+
+// The uniform geometry of xi item j.
+struct XItem {
+    unsigned F0, L0, f0, a1, a2, count;
+};
+
+__device__ __forceinline__ XItem x_item(const GeoK& G, long j, int W) {
+    XItem it;
+    const unsigned nf = (unsigned)G.n[0] + 1, ne = (unsigned)G.n[0] + 8, n1 = (unsigned)G.n[1];
+    const unsigned total = nf * n1 * (unsigned)G.n[2];
+    it.F0 = (unsigned)((W - 1) * j);
+    it.L0 = it.F0 / nf;
+    it.f0 = it.F0 - it.L0 * nf;
+    it.a1 = it.L0 % n1;
+    it.a2 = it.L0 / n1;
+    const unsigned Fl = min(it.F0 + (unsigned)W - 1, total - 1);
+    const unsigned Ll = Fl / nf;
+    it.count = (Ll - it.L0) * ne + (Fl - Ll * nf) + 8 - it.f0;  // entries e(F0) .. e(Fl) + 7
+    return it;
+}
+
 // Stage item j's stencil entries into buf (all 64 lanes; asynchronous).
 template <int DIM>
 __device__ __forceinline__ void x_stage(const GeoK& G, const double* __restrict__ met, const double* qs,
@@ -183,26 +268,30 @@ __device__ __forceinline__ void x_stage(const GeoK& G, const double* __restrict_
     constexpr int NV = DIM + 2;
     constexpr int NMET = DIM == 3 ? 10 : 5;
     const unsigned lane = threadIdx.x & 63;
-    const unsigned n0 = (unsigned)G.n[0], nf = n0 + 1, ne = n0 + 8;
-    const unsigned nlines = (unsigned)G.n[1] * (unsigned)G.n[2];
-    const unsigned F0 = (unsigned)((W - 1) * j);
-    const unsigned L0 = F0 / nf;
-    const unsigned elo = L0 * ne + (F0 - L0 * nf);
+    const unsigned n0 = (unsigned)G.n[0], ne = n0 + 8, n1 = (unsigned)G.n[1], n2 = (unsigned)G.n[2];
+    const XItem it = x_item(G, j, W);
+    const float inv_ne = 1.0f / (float)ne;
     const int g = G.g;
     const int per = G.bc[0] == 0;
+    const unsigned np = (it.count + 31) / 32;
 #pragma unroll
     for (int p = 0; p < XLds<DIM>::NE / 32; ++p) {
-        const unsigned e = elo + 32u * p + (lane >> 1);
-        unsigned L = e / ne;
-        int x = (int)(e - L * ne) - 4;
-        if (L >= nlines) L = nlines - 1;  // entries past the last line are never read
+        if ((unsigned)p >= np) break;
+        const unsigned k = it.f0 + 32u * p + (lane >> 1);  // from the start of line L0's entries
+        const unsigned dL = small_div(k, inv_ne);
+        const int x = (int)(k - dL * ne) - 4;
+        unsigned l1, l2;
+        line_step(it.a1, it.a2, dL, n1, l1, l2);
+        if (l2 >= n2) {  // entries past the last line are never read
+            l1 = n1 - 1;
+            l2 = n2 - 1;
+        }
         const int xm = x < -g ? -g : (x > (int)n0 - 1 + g ? (int)n0 - 1 + g : x);
         int xq = xm;
         if (per) {
             xq = x < 0 ? x + (int)n0 : (x >= (int)n0 ? x - (int)n0 : x);
             xq = xq < 0 ? 0 : (xq > (int)n0 - 1 ? (int)n0 - 1 : xq);
         }
-        const unsigned l1 = L % (unsigned)G.n[1], l2 = L / (unsigned)G.n[1];
         const unsigned lb = (unsigned)G.base + l1 * (unsigned)G.sd[1] + l2 * (unsigned)G.sd[2];
         const unsigned oq = (lb + (unsigned)xq) * 8u + (lane & 1) * 4u;
         const unsigned om = (lb + (unsigned)xm) * 8u + (lane & 1) * 4u;
@@ -245,30 +334,29 @@ __device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, cons
                                           const double (*buf)[XLds<DIM>::NE]) {
     constexpr int NV = DIM + 2;
     const unsigned lane = threadIdx.x & 63;
-    const unsigned n0 = (unsigned)G.n[0], nf = n0 + 1, ne = n0 + 8;
+    const unsigned nf = (unsigned)G.n[0] + 1, ne = (unsigned)G.n[0] + 8;
     const unsigned total = nf * (unsigned)G.n[1] * (unsigned)G.n[2];
-    const unsigned F0 = (unsigned)((W - 1) * j);
-    const unsigned L0 = F0 / nf;
-    const unsigned elo = L0 * ne + (F0 - L0 * nf);
-    const unsigned F = F0 + lane;
+    const XItem it = x_item(G, j, W);
+    const unsigned F = it.F0 + lane;
     const bool active = lane < (unsigned)W && F < total;
     double fl[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) fl[v] = 0.0;
-    unsigned L = 0, f = 0;
+    const unsigned k = it.f0 + lane;  // from the first face of line L0
+    const unsigned dL = small_div(k, 1.0f / (float)nf);
+    const unsigned f = k - dL * nf;
     if (active) {
-        L = F / nf;
-        f = F - L * nf;
         XLoader<DIM> ld;
         ld.buf = buf;
-        ld.ea = (L * ne + f - elo) * 8u;
+        ld.ea = (dL * ne + f - it.f0) * 8u;
         face_flux<DIM, RECON, Y, char_t<PREC>>(ld, sk, fl);
     }
     double d[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) d[v] = fl[v] - __shfl_up(fl[v], 1, 64);
     if (active && lane > 0 && f > 0) {
-        const unsigned l1 = L % (unsigned)G.n[1], l2 = L / (unsigned)G.n[1];
+        unsigned l1, l2;
+        line_step(it.a1, it.a2, dL, (unsigned)G.n[1], l1, l2);
         const long lb = G.base + (long)l1 * G.sd[1] + (long)l2 * G.sd[2];
         epilogue<NV>(ep, G.vol, lb + (f - 1), d);
     }
@@ -410,6 +498,14 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
     for (int it = 0; it < iters; ++it) {
         const int f = k0 - 1 + 4 * it + w;
         if (it + 1 < iters) load_row(tb + W::WIN + 4 * it + w);  // a row of the next iteration
+        // this wave's node f: its epilogue operands load while the face is
+        // computed, unless the face computation needs every register (WENO
+        // in FP64)
+        constexpr bool early = !(RECON == 0 && PREC == 0);
+        const bool mine = lane_ok && f >= k0 && f < k1;
+        const long noff = lb + (long)f * G.sd[DIR];
+        EpiPre<NV> pre;
+        if (early && mine) epi_load<NV>(ep, G.vol, noff, pre);
         double F[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = 0.0;
@@ -424,12 +520,15 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
 #pragma unroll
         for (int v = 0; v < NV; ++v) L.flux[buf][w][v][lane] = F[v];
         __syncthreads();
-        if (lane_ok && f >= k0 && f < k1) {
+        if (mine) {
             const double* prev = w > 0 ? &L.flux[buf][w - 1][0][0] : &L.flux[buf ^ 1][3][0][0];
             double d[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) d[v] = F[v] - prev[v * 64 + lane];
-            epilogue<NV>(ep, G.vol, lb + (long)f * G.sd[DIR], d);
+            if (early)
+                epi_store<NV>(ep, G.vol, noff, pre, d);
+            else
+                epilogue<NV>(ep, G.vol, noff, d);
         }
         __builtin_amdgcn_s_waitcnt(0);  // this wave's row DMA has landed
         __syncthreads();                // every row of the next iteration is in LDS
@@ -484,6 +583,12 @@ struct BTab {
     int cap;
 };
 
+// Block of `item` at or after block b, for items that only increase.
+__device__ __forceinline__ int advance_block(const long* st, int nblk, int b, long item) {
+    while (b + 1 < nblk && st[b + 1] <= item) ++b;
+    return b;
+}
+
 // Largest b in [0, nblk) with st[b] <= item (blocks without items of a kind
 // have st[b] == st[b + 1] and are skipped).
 __device__ __forceinline__ int find_block(const long* st, int nblk, long item) {
@@ -533,23 +638,25 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(BTab t, SchemeK 
     const long nw = (long)gridDim.x * 4;
     long item = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
     int cur = 0;
+    int b = 0;
     if (item < total) {
-        const int b = find_block(st, nblk, item);
+        b = find_block(st, nblk, item);
         const BBlock& B = t.blk[b];
         x_stage<DIM>(B.G, B.met, stage_in(B, stage), item - st[b], x_window(B.G.n[0]), L.b[0]);
     }
     for (; item < total; item += nw, cur ^= 1) {
         __builtin_amdgcn_s_waitcnt(0);
         asm volatile("" ::: "memory");
+        int bn = b;
         if (item + nw < total) {
-            const int bn = find_block(st, nblk, item + nw);
+            bn = advance_block(st, nblk, b, item + nw);
             const BBlock& N = t.blk[bn];
             x_stage<DIM>(N.G, N.met, stage_in(N, stage), item + nw - st[bn], x_window(N.G.n[0]), L.b[cur ^ 1]);
         }
-        const int b = find_block(st, nblk, item);
         const BBlock& B = t.blk[b];
         const EpiK ep = stage_epi(B, stage, EPI_FIRST, DIM);
         x_compute<DIM, RECON, Y, PREC>(B.G, sk, ep, item - st[b], x_window(B.G.n[0]), L.b[cur]);
+        b = bn;
     }
 }
 
@@ -563,8 +670,9 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_wg(BTab t, SchemeK
     const int nblk = *t.nblk;
     const long* st = t.start + KIND * (t.cap + 1);
     const long total = st[nblk];
+    int b = blockIdx.x < total ? find_block(st, nblk, blockIdx.x) : 0;
     for (long item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_block(st, nblk, item);
+        b = advance_block(st, nblk, b, item);
         const BBlock& B = t.blk[b];
         const EpiK ep = stage_epi(B, stage, MODE, DIM);
         sweep_wg_item<DIM, DIR, RECON, Y, PREC>(B.G, sk, B.met, stage_in(B, stage), ep, B.S[DIR],

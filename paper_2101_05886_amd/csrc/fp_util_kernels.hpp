@@ -138,34 +138,48 @@ __global__ __launch_bounds__(256) void k_periodic_fill(GeoK G, int ndim, int nva
     for (int v = 0; v < nvar; ++v) a[v * G.vol + tid] = a[v * G.vol + src];
 }
 
-// Copies the ghost layers of the frozen axes (nodes outside the interior
-// along a frozen axis, interior along the others: the only ghost nodes the
-// sweeps read) of src into dst1 and dst2, for the node with flat index tid.
-// The RK3 drivers use it to give their stage registers the caller's boundary
-// values.
-__device__ __forceinline__ void frozen_ghost_node(const GeoK& G, int ndim, int nvar, const double* src,
-                                                  double* dst1, double* dst2, long tid) {
-    if (tid >= G.vol) return;
-    int N[3];
-    N[0] = G.n[0] + 2 * G.g;
-    N[1] = G.n[1] + 2 * G.g;
-    N[2] = ndim == 3 ? G.n[2] + 2 * G.g : 1;
-    int p[3];
-    p[0] = (int)(tid % N[0]) - G.g;
-    p[1] = (int)((tid / N[0]) % N[1]) - G.g;
-    p[2] = ndim == 3 ? (int)(tid / ((long)N[0] * N[1])) - G.g : 0;
-    int outside = 0, frozen_out = 0;
+// Nodes of the ghost slabs of the frozen axes: for each frozen axis d, the
+// g layers on each side along d with the other coordinates interior (the
+// only ghost nodes the sweeps read).
+__host__ __device__ inline long frozen_slab_nodes(const GeoK& G, int ndim) {
+    long tot = 0;
     for (int d = 0; d < ndim; ++d) {
-        if (p[d] < 0 || p[d] >= G.n[d]) {
-            ++outside;
-            if (G.bc[d] != 0) frozen_out = 1;
-        }
+        if (G.bc[d] == 0) continue;
+        long c = 2L * G.g;
+        for (int e = 0; e < ndim; ++e)
+            if (e != d) c *= G.n[e];
+        tot += c;
     }
-    if (outside != 1 || !frozen_out) return;
-    for (int v = 0; v < nvar; ++v) {
-        const double x = src[v * G.vol + tid];
-        dst1[v * G.vol + tid] = x;
-        dst2[v * G.vol + tid] = x;
+    return tot;
+}
+
+// Copies slab node t (0 <= t < frozen_slab_nodes) of src into dst1 and dst2:
+// the RK3 drivers give their stage registers the caller's boundary values.
+__device__ __forceinline__ void frozen_ghost_node(const GeoK& G, int ndim, int nvar, const double* src,
+                                                  double* dst1, double* dst2, long t) {
+    for (int d = 0; d < ndim; ++d) {
+        if (G.bc[d] == 0) continue;
+        long c = 2L * G.g;
+        for (int e = 0; e < ndim; ++e)
+            if (e != d) c *= G.n[e];
+        if (t >= c) {
+            t -= c;
+            continue;
+        }
+        const int ad = (int)(t % (2 * G.g));
+        long rest = t / (2 * G.g);
+        long off = G.base + (long)(ad < G.g ? ad - G.g : G.n[d] + ad - G.g) * G.sd[d];
+        for (int e = 0; e < ndim; ++e) {
+            if (e == d) continue;
+            off += (rest % G.n[e]) * G.sd[e];
+            rest /= G.n[e];
+        }
+        for (int v = 0; v < nvar; ++v) {
+            const double x = src[v * G.vol + off];
+            dst1[v * G.vol + off] = x;
+            dst2[v * G.vol + off] = x;
+        }
+        return;
     }
 }
 
@@ -173,18 +187,22 @@ __global__ __launch_bounds__(256) void k_frozen_ghosts(GeoK G, int ndim, int nva
                                                        const double* __restrict__ src,
                                                        double* __restrict__ dst1,
                                                        double* __restrict__ dst2) {
-    frozen_ghost_node(G, ndim, nvar, src, dst1, dst2, (long)blockIdx.x * blockDim.x + threadIdx.x);
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < frozen_slab_nodes(G, ndim)) frozen_ghost_node(G, ndim, nvar, src, dst1, dst2, t);
 }
 
-// Batched form: one item = 256 nodes of one block's ghost-copy range.
+// Batched form: one item = 256 slab nodes of one block.
 __global__ __launch_bounds__(256) void kb_frozen_ghosts(BTab t, int ndim) {
     const int nblk = *t.nblk;
     const long* st = t.start + BK_GHOST * (t.cap + 1);
     const long total = st[nblk];
+    int b = blockIdx.x < total ? find_block(st, nblk, blockIdx.x) : 0;
     for (long item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_block(st, nblk, item);
+        b = advance_block(st, nblk, b, item);
         const BBlock& B = t.blk[b];
-        frozen_ghost_node(B.G, ndim, ndim + 2, B.q, B.A, B.B, (item - st[b]) * 256 + threadIdx.x);
+        const long node = (item - st[b]) * 256 + threadIdx.x;
+        if (node < frozen_slab_nodes(B.G, ndim))
+            frozen_ghost_node(B.G, ndim, ndim + 2, B.q, B.A, B.B, node);
     }
 }
 
