@@ -381,7 +381,8 @@ hipError_t run_batch_step(const fp_batch* b, int mask, hipStream_t s) {
     for (int p = 0; p < 2; ++p) {
         if (!(mask & (1 << p))) continue;
         const int ndim = p == 0 ? 2 : 3;
-        hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p], ndim);
+        hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p].nblk,
+                           b->tab[p].start, b->tab[p].blk, b->tab[p].cap, ndim);
         for (int k = 0; k < 3; ++k) {
             hipError_t e = b->fn[p](b->tab[p], b->sk, k, b->grid[p], -1, s);
             if (e != hipSuccess) return e;
@@ -856,8 +857,8 @@ fp_status fp_batch_profile_step(fp_batch* b, float* kernel_ms, int32_t* kernel_k
     for (int i = 0; i < n && e == hipSuccess; ++i) {
         const int p = plan[i][0], kind = plan[i][1], k = plan[i][2];
         if (kind == BK_GHOST)
-            hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p],
-                               p == 0 ? 2 : 3);
+            hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p].nblk,
+                               b->tab[p].start, b->tab[p].blk, b->tab[p].cap, p == 0 ? 2 : 3);
         else
             e = b->fn[p](b->tab[p], b->sk, k, b->grid[p], kind, s);
         if (e == hipSuccess) e = hipGetLastError();

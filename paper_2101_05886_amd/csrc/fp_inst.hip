@@ -124,12 +124,15 @@ template <int DIM, int Y>
 hipError_t run_batch_stage(const BTab& t, const SchemeK& sk, int stage, const int grid[3], int only,
                            hipStream_t s) {
     if (only < 0 || only == BK_X)
-        hipLaunchKernelGGL((kb_sweep_x<DIM, R, Y, P>), dim3(grid[0]), dim3(256), 0, s, t, sk, stage);
+        hipLaunchKernelGGL((kb_sweep_x<DIM, R, Y, P>), dim3(grid[0]), dim3(256), 0, s, t.nblk, t.start, t.blk,
+                           t.cap, sk, stage);
     if (only < 0 || only == BK_ETA)
-        hipLaunchKernelGGL((kb_sweep_wg<DIM, 1, R, Y, P>), dim3(grid[1]), dim3(256), 0, s, t, sk, stage);
+        hipLaunchKernelGGL((kb_sweep_wg<DIM, 1, R, Y, P>), dim3(grid[1]), dim3(256), 0, s, t.nblk, t.start,
+                           t.blk, t.cap, sk, stage);
     if constexpr (DIM == 3)
         if (only < 0 || only == BK_ZETA)
-            hipLaunchKernelGGL((kb_sweep_wg<3, 2, R, Y, P>), dim3(grid[2]), dim3(256), 0, s, t, sk, stage);
+            hipLaunchKernelGGL((kb_sweep_wg<3, 2, R, Y, P>), dim3(grid[2]), dim3(256), 0, s, t.nblk, t.start,
+                               t.blk, t.cap, sk, stage);
     return hipGetLastError();
 }
 

@@ -189,6 +189,10 @@ __device__ __forceinline__ void dma_dword(const double* var, void* lds, unsigned
                                      (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
 }
 
+// The wave's index in its workgroup, as a value the compiler knows to be
+// uniform across the wave (so what derives from it stays in scalar registers).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // ---------------------------------------------------------------------------
 // xi sweep
 // ---------------------------------------------------------------------------
@@ -369,11 +373,11 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK s
                                                                const double* __restrict__ met,
                                                                const double* qs, EpiK ep) {
     __shared__ XLds<DIM> lds[4];
-    XLds<DIM>& L = lds[threadIdx.x >> 6];
+    XLds<DIM>& L = lds[wave_id()];
     const long nw = (long)gridDim.x * 4;
     const long items = sweep_x_items(G.n);
     const int W = x_window(G.n[0]);
-    long j = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    long j = (long)blockIdx.x * 4 + wave_id();
     int cur = 0;
     if (j < items) x_stage<DIM>(G, met, qs, j, W, L.b[0]);
     for (; j < items; j += nw, cur ^= 1) {
@@ -447,7 +451,7 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
     constexpr int NMET = DIM == 3 ? 10 : 5;
     constexpr int OTH = DIR == 1 ? 2 : 1;
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = wave_id();
     const long nlines = (long)G.n[0] * G.n[OTH];
     const long lblocks = (nlines + 63) / 64;
     const long lineblk = item % lblocks;
@@ -629,19 +633,22 @@ __device__ __forceinline__ EpiK stage_epi(const BBlock& b, int stage, int mode, 
 // batch's wave items w, w + (waves of the grid), ..., staging the next item
 // (possibly of another block) while it computes.
 template <int DIM, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(BTab t, SchemeK sk, int stage) {
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(const int* __restrict__ t_nblk,
+                                                                const long* __restrict__ t_start,
+                                                                const BBlock* __restrict__ t_blk, int cap,
+                                                                SchemeK sk, int stage) {
     __shared__ XLds<DIM> lds[4];
-    XLds<DIM>& L = lds[threadIdx.x >> 6];
-    const int nblk = *t.nblk;
-    const long* st = t.start + BK_X * (t.cap + 1);
+    XLds<DIM>& L = lds[wave_id()];
+    const int nblk = *t_nblk;
+    const long* __restrict__ st = t_start + BK_X * (cap + 1);
     const long total = st[nblk];
     const long nw = (long)gridDim.x * 4;
-    long item = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    long item = (long)blockIdx.x * 4 + wave_id();
     int cur = 0;
     int b = 0;
     if (item < total) {
         b = find_block(st, nblk, item);
-        const BBlock& B = t.blk[b];
+        const BBlock& B = t_blk[b];
         x_stage<DIM>(B.G, B.met, stage_in(B, stage), item - st[b], x_window(B.G.n[0]), L.b[0]);
     }
     for (; item < total; item += nw, cur ^= 1) {
@@ -650,10 +657,10 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(BTab t, SchemeK 
         int bn = b;
         if (item + nw < total) {
             bn = advance_block(st, nblk, b, item + nw);
-            const BBlock& N = t.blk[bn];
+            const BBlock& N = t_blk[bn];
             x_stage<DIM>(N.G, N.met, stage_in(N, stage), item + nw - st[bn], x_window(N.G.n[0]), L.b[cur ^ 1]);
         }
-        const BBlock& B = t.blk[b];
+        const BBlock& B = t_blk[b];
         const EpiK ep = stage_epi(B, stage, EPI_FIRST, DIM);
         x_compute<DIM, RECON, Y, PREC>(B.G, sk, ep, item - st[b], x_window(B.G.n[0]), L.b[cur]);
         b = bn;
@@ -663,17 +670,20 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(BTab t, SchemeK 
 // Persistent batched eta / zeta sweep of one RK stage; the last direction
 // applies the RK3 update.
 template <int DIM, int DIR, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_wg(BTab t, SchemeK sk, int stage) {
+__global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_wg(const int* __restrict__ t_nblk,
+                                                                 const long* __restrict__ t_start,
+                                                                 const BBlock* __restrict__ t_blk, int cap,
+                                                                 SchemeK sk, int stage) {
     __shared__ WgLds<DIM, Y> lds;
     constexpr int KIND = DIR == 1 ? BK_ETA : BK_ZETA;
     constexpr int MODE = DIR == DIM - 1 ? EPI_LAST_RK : EPI_MID;
-    const int nblk = *t.nblk;
-    const long* st = t.start + KIND * (t.cap + 1);
+    const int nblk = *t_nblk;
+    const long* __restrict__ st = t_start + KIND * (cap + 1);
     const long total = st[nblk];
     int b = blockIdx.x < total ? find_block(st, nblk, blockIdx.x) : 0;
     for (long item = blockIdx.x; item < total; item += gridDim.x) {
         b = advance_block(st, nblk, b, item);
-        const BBlock& B = t.blk[b];
+        const BBlock& B = t_blk[b];
         const EpiK ep = stage_epi(B, stage, MODE, DIM);
         sweep_wg_item<DIM, DIR, RECON, Y, PREC>(B.G, sk, B.met, stage_in(B, stage), ep, B.S[DIR],
                                                 item - st[b], lds);

@@ -192,14 +192,16 @@ __global__ __launch_bounds__(256) void k_frozen_ghosts(GeoK G, int ndim, int nva
 }
 
 // Batched form: one item = 256 slab nodes of one block.
-__global__ __launch_bounds__(256) void kb_frozen_ghosts(BTab t, int ndim) {
-    const int nblk = *t.nblk;
-    const long* st = t.start + BK_GHOST * (t.cap + 1);
+__global__ __launch_bounds__(256) void kb_frozen_ghosts(const int* __restrict__ t_nblk,
+                                                        const long* __restrict__ t_start,
+                                                        const BBlock* __restrict__ t_blk, int cap, int ndim) {
+    const int nblk = *t_nblk;
+    const long* __restrict__ st = t_start + BK_GHOST * (cap + 1);
     const long total = st[nblk];
     int b = blockIdx.x < total ? find_block(st, nblk, blockIdx.x) : 0;
     for (long item = blockIdx.x; item < total; item += gridDim.x) {
         b = advance_block(st, nblk, b, item);
-        const BBlock& B = t.blk[b];
+        const BBlock& B = t_blk[b];
         const long node = (item - st[b]) * 256 + threadIdx.x;
         if (node < frozen_slab_nodes(B.G, ndim))
             frozen_ghost_node(B.G, ndim, ndim + 2, B.q, B.A, B.B, node);
