@@ -9,7 +9,9 @@ replayed from the library's captured step graph.
 
 Default workload (c4): 48 uneven O-grid blocks advanced together by the
 batched path, FP32-mixed reconstruction as `value`, FP64 timed beside it
-(`fp64`, `mixed_over_fp64`).  Single-block workloads: --workload c1/c2/c3/c3m.
+(`fp64`, `mixed_over_fp64`), and the serving stream (500 requests, p50/p99
+latency) reported under `serving` (--no-serving skips it).  Single-block
+workloads: --workload c1/c2/c3/c3m; the serving stream alone: --workload c5.
 
 Prints ONE JSON line.  Extra fields: the per-kernel roofline of the dominant
 sweep kernel (timed with HIP events on the stream it runs on), the
@@ -221,6 +223,7 @@ def bench_batch(args, w):
         per_kernel[prec] = {k: sum(v) / len(v) for k, v in kinds.items()}
         res[prec] = dict(value=nodes * 3 * args.steps / (ms * 1e-3), ms_step=ms / args.steps, seg=seg,
                          ok=flag_ok)
+        progress(f"batch {prec}: {res[prec]['value']:.3e} cell-stage/s (segment {seg})")
         b.close()
         del ent
         torch.cuda.empty_cache()
@@ -255,12 +258,21 @@ def bench_batch(args, w):
                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS},
         "state_ok": res["mixed"]["ok"] and res["fp64"]["ok"],
     }
+    if not args.no_serving:
+        out["serving"] = serve_measure(WORKLOADS["c5"])
     if not args.no_cpu_baseline:
+        progress("cpu baseline (FP64 oracle)")
         out["cpu_baseline"] = cpu_baseline_blocks(w, blocks, g)
     print(json.dumps(out), flush=True)
 
 
-def bench_serve(args, w):
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def serve_measure(w):
+    """The serving stream: closed-loop capacity on the first requests, then
+    the open-loop Poisson stream at w['load'] x that capacity."""
     import torch
     from paper_2101_05886_amd import fp
     from paper_2101_05886_amd import serve as S
@@ -282,21 +294,31 @@ def bench_serve(args, w):
     closed = run(S.make_requests(w["capacity_requests"], seed=w["seed"], rate=None))
     cap = closed.summary()["requests_per_s"]
     rate = w["load"] * cap
+    progress(f"serving: closed-loop capacity {cap:.2f} requests/s; open loop at {rate:.2f}/s")
     st = run(S.make_requests(w["requests"], seed=w["seed"], rate=rate))
     s = st.summary()
+    progress(f"serving: {s['requests']} requests, p50 {s['p50_latency_s']:.2f} s, p99 {s['p99_latency_s']:.2f} s")
+    return {"workload": w["name"], "requests": w["requests"], "slots": w["slots"],
+            "round_steps": w["round_steps"], "hbm_budget_bytes": budget,
+            "cell_stage_per_s": s["cell_stage_per_s"],
+            "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
+            "requests_per_s": s["requests_per_s"], "mean_queue_wait_s": s["mean_queue_wait_s"],
+            "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": cap,
+            "closed_loop_cell_stage_per_s": closed.summary()["cell_stage_per_s"],
+            "makespan_s": s["makespan_s"], "rounds": s["rounds"], "peak_active": s["peak_active"],
+            "peak_bytes": s["peak_bytes"]}
+
+
+def bench_serve(args, w):
+    sv = serve_measure(w)
     out = {
-        "metric": "cell-stage updates/s", "value": s["cell_stage_per_s"], "unit": "cell-stage updates/s",
+        "metric": "cell-stage updates/s", "value": sv["cell_stage_per_s"], "unit": "cell-stage updates/s",
         "n_gpus": 1, "steps": 200, "warmup": 0, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 state, f32 reconstruction", "data": "synthetic",
         "config": {"workload": w["name"], "requests": w["requests"], "slots": w["slots"],
-                   "round_steps": w["round_steps"], "hbm_budget_bytes": budget},
-        "serving": {"p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
-                    "requests_per_s": s["requests_per_s"], "mean_queue_wait_s": s["mean_queue_wait_s"],
-                    "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": cap,
-                    "closed_loop_cell_stage_per_s": closed.summary()["cell_stage_per_s"],
-                    "makespan_s": s["makespan_s"], "rounds": s["rounds"], "peak_active": s["peak_active"],
-                    "peak_bytes": s["peak_bytes"]},
+                   "round_steps": w["round_steps"], "hbm_budget_bytes": sv["hbm_budget_bytes"]},
+        "serving": sv,
     }
     print(json.dumps(out), flush=True)
 
@@ -322,6 +344,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="batched workload only: skip the serving stream reported beside it")
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (the reference "

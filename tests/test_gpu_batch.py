@@ -209,3 +209,36 @@ def test_batch_profile_step_is_a_step():
     for i, k in enumerate(blocks):
         assert torch.equal(k.q, k.alone(sc, 1)), f"block {i}"
     b.close()
+
+
+def test_c4_full_size_blocks_match_oracle():
+    """The 48-block workload at full size with a perturbed (non-uniform)
+    state: after one batched step, two blocks (the largest and a small one)
+    against the FP64 oracle stepping the same block from the GPU's metrics."""
+    sc = fp.Scheme("weno5", 6, True)
+    specs = I.multiblock_specs(48, seed=4)
+    blocks = []
+    for i, spec in enumerate(specs):
+        g, Y = 3, 6
+        xyz = I.ogrid_sector_block(spec.n, g, Y, spec.sector, spec.skew_deg, spec.rotation)
+        q = I.uniform_state(3, spec.n, g, G.GAMMA, I.mach_velocity(3.0, [1.0, 0.0, 0.0]), 1.0)
+        rng = np.random.Generator(np.random.PCG64(100 + i))
+        q = np.ascontiguousarray(q * (1.0 + 0.01 * rng.standard_normal(q.shape)))
+        blocks.append(Block(dict(ndim=3, n=list(spec.n), g=g, Y=Y, bc=[1, 1, 1], xyz=xyz, q=q), sc))
+    b = fp.Batch(sc, 48)
+    b.set([k.entry() for k in blocks])
+    b.rk3_step()
+    torch.cuda.synchronize()
+    sizes = [int(np.prod(k.grid.n)) for k in blocks]
+    for i in (int(np.argmax(sizes)), int(np.argmin(sizes))):
+        k = blocks[i]
+        c = k.case
+        og = O.Grid(3, c["n"], c["g"], bc=[1, 1, 1])
+        ref = O.rk3_step(og, O.Scheme("weno5", 6, True), k.met.cpu().numpy(), c["q"], k.dt)
+        got = k.q.cpu().numpy()
+        sl = (slice(None),) + (slice(c["g"], -c["g"]),) * 3
+        for v in range(5):
+            err = np.abs(got[sl][v] - ref[sl][v]).max() / np.abs(ref[sl][v]).max()
+            print(f"C4 block {i} {c['n']} variable {v}: {err:.2e}", flush=True)
+            assert err <= 1e-12
+    b.close()
