@@ -547,8 +547,61 @@ double fpo_linear_upwind5(const double v[5])
     return (2.0 * v[0] - 13.0 * v[1] + 47.0 * v[2] + 27.0 * v[3] - 3.0 * v[4]) / 60.0;
 }
 
-static double reconstruct(const fpo_scheme *sc, const double v[5])
+/* WENO7-JS (the standard seventh-order WENO the paper extends its method to,
+ * Remark 2): v = (f_{i-3} .. f_{i+3}), four third-degree candidates on
+ * {i-3..i}, {i-2..i+1}, {i-1..i+2}, {i..i+3}, optimal weights
+ * (1, 12, 18, 4)/35, and smoothness indicators that are the integer
+ * quadratic forms equal to 240 x the Jiang-Shu measure
+ * sum_{l=1}^{3} int_cell (d^l p_k / dx^l)^2 dx (unit spacing).  Reading:
+ * the forms are used without the 1/240 (with eps = 1e-6 this reproduces the
+ * WENO7 rows of Table 2; the normalised measure does not).  The weights are
+ * C_k / (beta_k + eps)^2 as for WENO5. */
+void fpo_weno7_parts(const double v[7], double q[4], double beta[4])
 {
+    const double a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5], g = v[6];
+    q[0] = (-3.0 * a + 13.0 * b - 23.0 * c + 25.0 * d) / 12.0;
+    q[1] = (b - 5.0 * c + 13.0 * d + 3.0 * e) / 12.0;
+    q[2] = (-c + 7.0 * d + 7.0 * e - f) / 12.0;
+    q[3] = (3.0 * d + 13.0 * e - 5.0 * f + g) / 12.0;
+    beta[0] = (a * (547.0 * a - 3882.0 * b + 4642.0 * c - 1854.0 * d)
+               + b * (7043.0 * b - 17246.0 * c + 7042.0 * d)
+               + c * (11003.0 * c - 9402.0 * d) + 2107.0 * d * d);
+    beta[1] = (b * (267.0 * b - 1642.0 * c + 1602.0 * d - 494.0 * e)
+               + c * (2843.0 * c - 5966.0 * d + 1922.0 * e)
+               + d * (3443.0 * d - 2522.0 * e) + 547.0 * e * e);
+    beta[2] = (c * (547.0 * c - 2522.0 * d + 1922.0 * e - 494.0 * f)
+               + d * (3443.0 * d - 5966.0 * e + 1602.0 * f)
+               + e * (2843.0 * e - 1642.0 * f) + 267.0 * f * f);
+    beta[3] = (d * (2107.0 * d - 9402.0 * e + 7042.0 * f - 1854.0 * g)
+               + e * (11003.0 * e - 17246.0 * f + 4642.0 * g)
+               + f * (7043.0 * f - 3882.0 * g) + 547.0 * g * g);
+}
+
+double fpo_weno7(const double v[7], double eps)
+{
+    const double C[4] = {1.0 / 35.0, 12.0 / 35.0, 18.0 / 35.0, 4.0 / 35.0};
+    double q[4], beta[4], alpha[4], asum = 0.0, out = 0.0;
+    fpo_weno7_parts(v, q, beta);
+    for (int k = 0; k < 4; k++) {
+        alpha[k] = C[k] / pow(beta[k] + eps, 2);
+        asum += alpha[k];
+    }
+    for (int k = 0; k < 4; k++)
+        out += alpha[k] / asum * q[k];
+    return out;
+}
+
+/* half-width of the split-flux stencil below the face node i: the "+" part
+ * uses f_{i-lo} .. f_{i+lo}, the "-" part f_{i+lo+1} .. f_{i-lo+1} */
+static int stencil_lo(const fpo_scheme *sc)
+{
+    return sc->recon == 2 ? 3 : 2;
+}
+
+static double reconstruct(const fpo_scheme *sc, const double *v)
+{
+    if (sc->recon == 2)
+        return fpo_weno7(v, sc->eps);
     return sc->recon == 1 ? fpo_linear_upwind5(v) : fpo_weno5(v, sc->eps);
 }
 
@@ -603,13 +656,15 @@ static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, double *Fp)
             Fts[v] += Fs[c][v] * sf[c];
     }
 
-    /* (3) reference-subtracted stencil values, m = i-2 .. i+3:
+    /* (3) reference-subtracted stencil values, m = i-lo .. i+lo+1 (lo = 2 for
+     * the fifth-order schemes, 3 for WENO7):
      * dQ~_m = (Q_m - Q*)/J_m and
      * dF~_m = (F_m - F*) (xi_x/J)_m + (G_m - G*) (xi_y/J)_m + (H_m - H*) (xi_z/J)_m
      * (eqs. Linear_upwind_LFspliting and flux_split_detail) */
-    double dQt[6][NVMAX], dFt[6][NVMAX];
-    for (int r = 0; r < 6; r++) {
-        int m = i - 2 + r;
+    const int lo = stencil_lo(sc), ns = 2 * lo + 2;
+    double dQt[8][NVMAX], dFt[8][NVMAX];
+    for (int r = 0; r < ns; r++) {
+        int m = i - lo + r;
         double Qm[NVMAX], Fm[3][NVMAX];
         for (int v = 0; v < nv; v++)
             Qm[v] = ln->Q[v][m];
@@ -632,13 +687,13 @@ static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, double *Fp)
     roe_system(ndim, gam, QL, QR, sf, Vf, &S);
 
     /* (5) local Lax-Friedrichs speed of every field: the largest
-     * sigma |n . u_m + kappa_s c_m| over the stencil m = i-2 .. i+3 */
+     * sigma |n . u_m + kappa_s c_m| over the stencil m = i-lo .. i+lo+1 */
     double lam[NVMAX];
     for (int s = 0; s < nv; s++) {
         double kap = s == 0 ? -1.0 : (s == nv - 1 ? 1.0 : 0.0);
         lam[s] = 0.0;
-        for (int r = 0; r < 6; r++) {
-            int m = i - 2 + r;
+        for (int r = 0; r < ns; r++) {
+            int m = i - lo + r;
             double Qm[NVMAX];
             for (int v = 0; v < nv; v++)
                 Qm[v] = ln->Q[v][m];
@@ -654,9 +709,9 @@ static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, double *Fp)
 
     /* (6) characteristic projection and Lax-Friedrichs splitting:
      * F~^{s,+-}_m = 1/2 l_s . (dF~_m +- lambda_s dQ~_m) */
-    double vp[NVMAX][6], vm[NVMAX][6];
+    double vp[NVMAX][8], vm[NVMAX][8];
     for (int s = 0; s < nv; s++)
-        for (int r = 0; r < 6; r++) {
+        for (int r = 0; r < ns; r++) {
             double a = 0.0, b = 0.0;
             for (int v = 0; v < nv; v++) {
                 a += S.L[s][v] * dFt[r][v];
@@ -667,11 +722,14 @@ static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, double *Fp)
         }
 
     /* (7) reconstruction of both split parts at the face: the "+" part from
-     * m = i-2 .. i+2, the "-" part mirrored from m = i+3 .. i-1 */
+     * m = i-lo .. i+lo, the "-" part mirrored from m = i+lo+1 .. i-lo+1 */
     double hp[NVMAX], hm[NVMAX];
     for (int s = 0; s < nv; s++) {
-        double a[5] = {vp[s][0], vp[s][1], vp[s][2], vp[s][3], vp[s][4]};
-        double b[5] = {vm[s][5], vm[s][4], vm[s][3], vm[s][2], vm[s][1]};
+        double a[7], b[7];
+        for (int r = 0; r < ns - 1; r++) {
+            a[r] = vp[s][r];
+            b[r] = vm[s][ns - 1 - r];
+        }
         hp[s] = reconstruct(sc, a);
         hm[s] = reconstruct(sc, b);
     }
@@ -742,12 +800,13 @@ static void gather_line(const layout *L, const double *q, const double *met, int
 
 static int check_scheme(const layout *L, const fpo_scheme *sc)
 {
-    if (!sc || (sc->recon != 0 && sc->recon != 1) || (sc->reformulated != 0 && sc->reformulated != 1))
+    if (!sc || sc->recon < 0 || sc->recon > 2 || (sc->reformulated != 0 && sc->reformulated != 1))
         return -1;
     if (sc->Y != 2 && sc->Y != 4 && sc->Y != 6 && sc->Y != 8)
         return -1;
-    /* the stencil reaches 3 nodes; the face interpolation Y/2 nodes */
-    if (L->g < 3 || L->g < sc->Y / 2)
+    /* the split-flux stencil reaches lo + 1 nodes from a node (3 for the
+     * fifth-order schemes, 4 for WENO7); the face interpolation Y/2 nodes */
+    if (L->g < stencil_lo(sc) + 1 || L->g < sc->Y / 2)
         return -1;
     if (!(sc->gamma > 1.0) || !(sc->eps > 0.0))
         return -1;
