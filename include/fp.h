@@ -65,7 +65,7 @@ typedef enum {
     FP_ENONPHYS = -5       /* reserved for state checks reported to the host */
 } fp_status;
 
-enum { FP_WENO5JS = 0, FP_LINUP5 = 1 };          /* reconstruction */
+enum { FP_WENO5JS = 0, FP_LINUP5 = 1, FP_WENO7JS = 2 };  /* reconstruction */
 enum { FP_FP64 = 0, FP_MIXED32 = 1 };            /* precision of the characteristic part */
 enum { FP_BC_PERIODIC = 0, FP_BC_FROZEN = 1 };   /* per axis */
 

@@ -26,34 +26,35 @@ namespace fpk {
     faceflux_fn get_faceflux_p##P##_r##R(int ndim, int dir, int Y);
 FP_DECL_GET(0, 0)
 FP_DECL_GET(0, 1)
+FP_DECL_GET(0, 2)
 FP_DECL_GET(1, 0)
 FP_DECL_GET(1, 1)
+FP_DECL_GET(1, 2)
 #undef FP_DECL_GET
 
 stage_fn get_stage_fn(int ndim, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_stage_p0_r0(ndim, Y) : get_stage_p0_r1(ndim, Y);
-    return recon == 0 ? get_stage_p1_r0(ndim, Y) : get_stage_p1_r1(ndim, Y);
+    if (prec == 0) return recon == 0 ? get_stage_p0_r0(ndim, Y) : recon == 1 ? get_stage_p0_r1(ndim, Y) : get_stage_p0_r2(ndim, Y);
+    return recon == 0 ? get_stage_p1_r0(ndim, Y) : recon == 1 ? get_stage_p1_r1(ndim, Y) : get_stage_p1_r2(ndim, Y);
 }
 
 dir_fn get_dir_fn(int ndim, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_dir_p0_r0(ndim, Y) : get_dir_p0_r1(ndim, Y);
-    return recon == 0 ? get_dir_p1_r0(ndim, Y) : get_dir_p1_r1(ndim, Y);
+    if (prec == 0) return recon == 0 ? get_dir_p0_r0(ndim, Y) : recon == 1 ? get_dir_p0_r1(ndim, Y) : get_dir_p0_r2(ndim, Y);
+    return recon == 0 ? get_dir_p1_r0(ndim, Y) : recon == 1 ? get_dir_p1_r1(ndim, Y) : get_dir_p1_r2(ndim, Y);
 }
 
 batch_stage_fn get_batch_stage_fn(int ndim, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_batch_stage_p0_r0(ndim, Y) : get_batch_stage_p0_r1(ndim, Y);
-    return recon == 0 ? get_batch_stage_p1_r0(ndim, Y) : get_batch_stage_p1_r1(ndim, Y);
+    if (prec == 0) return recon == 0 ? get_batch_stage_p0_r0(ndim, Y) : recon == 1 ? get_batch_stage_p0_r1(ndim, Y) : get_batch_stage_p0_r2(ndim, Y);
+    return recon == 0 ? get_batch_stage_p1_r0(ndim, Y) : recon == 1 ? get_batch_stage_p1_r1(ndim, Y) : get_batch_stage_p1_r2(ndim, Y);
 }
 
 batch_occ_fn get_batch_occ_fn(int ndim, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_batch_occ_p0_r0(ndim, Y) : get_batch_occ_p0_r1(ndim, Y);
-    return recon == 0 ? get_batch_occ_p1_r0(ndim, Y) : get_batch_occ_p1_r1(ndim, Y);
+    if (prec == 0) return recon == 0 ? get_batch_occ_p0_r0(ndim, Y) : recon == 1 ? get_batch_occ_p0_r1(ndim, Y) : get_batch_occ_p0_r2(ndim, Y);
+    return recon == 0 ? get_batch_occ_p1_r0(ndim, Y) : recon == 1 ? get_batch_occ_p1_r1(ndim, Y) : get_batch_occ_p1_r2(ndim, Y);
 }
 
 faceflux_fn get_faceflux_fn(int ndim, int dir, int recon, int Y, int prec) {
-    if (prec == 0)
-        return recon == 0 ? get_faceflux_p0_r0(ndim, dir, Y) : get_faceflux_p0_r1(ndim, dir, Y);
-    return recon == 0 ? get_faceflux_p1_r0(ndim, dir, Y) : get_faceflux_p1_r1(ndim, dir, Y);
+    if (prec == 0) return recon == 0 ? get_faceflux_p0_r0(ndim, dir, Y) : recon == 1 ? get_faceflux_p0_r1(ndim, dir, Y) : get_faceflux_p0_r2(ndim, dir, Y);
+    return recon == 0 ? get_faceflux_p1_r0(ndim, dir, Y) : recon == 1 ? get_faceflux_p1_r1(ndim, dir, Y) : get_faceflux_p1_r2(ndim, dir, Y);
 }
 
 }  // namespace fpk
@@ -99,11 +100,13 @@ fp_status check_grid(const fp_grid* g) {
 
 fp_status check_scheme(const fp_grid* g, const fp_scheme* s) {
     if (!s) return fail(FP_EINVAL, "scheme is NULL");
-    if (s->recon != FP_WENO5JS && s->recon != FP_LINUP5) return fail(FP_EINVAL, "unknown recon %d", s->recon);
+    if (s->recon != FP_WENO5JS && s->recon != FP_LINUP5 && s->recon != FP_WENO7JS)
+        return fail(FP_EINVAL, "unknown recon %d", s->recon);
     const int Y = s->metric_order;
     if (Y != 2 && Y != 4 && Y != 6 && Y != 8)
         return fail(FP_EUNSUPPORTED, "metric_order must be 2, 4, 6 or 8 (got %d)", Y);
     if (g->ghost < Y / 2) return fail(FP_EINVAL, "metric_order %d needs ghost >= %d", Y, Y / 2);
+    if (s->recon == FP_WENO7JS && g->ghost < 4) return fail(FP_EINVAL, "WENO7 needs ghost >= 4");
     if (s->reformulated != 0 && s->reformulated != 1) return fail(FP_EINVAL, "reformulated must be 0 or 1");
     if (s->precision != FP_FP64 && s->precision != FP_MIXED32)
         return fail(FP_EINVAL, "unknown precision %d", s->precision);
@@ -666,7 +669,7 @@ fp_status fp_batch_create(const fp_scheme* sch, int32_t max_blocks, fp_batch** o
     fp_grid g3{};
     g3.ndim = 3;
     g3.n[0] = g3.n[1] = g3.n[2] = 8;
-    g3.ghost = sch ? (sch->metric_order == 8 ? 4 : 3) : 3;
+    g3.ghost = sch ? ((sch->metric_order == 8 || sch->recon == FP_WENO7JS) ? 4 : 3) : 3;
     fp_status st = check_scheme(&g3, sch);
     if (st) return st;
     fp_batch* b = new fp_batch();

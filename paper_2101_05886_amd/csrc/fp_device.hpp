@@ -10,8 +10,9 @@
 //   B. Roe average of nodes i, i+1, unit normal, eigen-structure       [T]
 //   C. per stencil node m = i-2..i+3: reference-subtracted dQ~_m, dF~_m
 //      [FP64], local Lax-Friedrichs speeds, characteristic projections [T]
-//   D. WENO5-JS of both split parts of every field, or (linear upwind) the
-//      closed form central6(dF~) + (1/60) R Lambda L Delta^5(dQ~)      [T]
+//   D. WENO5-JS (or WENO7-JS on slots 0..7) of both split parts of every
+//      field, or (linear upwind) the closed form
+//      central6(dF~) + (1/60) R Lambda L Delta^5(dQ~)                  [T]
 //   E. back-projection and add-back of F~*_f                   [T, FP64 add]
 // T is double for the FP64 path and float for the mixed path.
 #pragma once
@@ -140,6 +141,39 @@ __device__ __forceinline__ float weno5(float a, float b, float c, float d, float
     const float a1 = 0.6f * fast_rcp(d1 * d1);
     const float a2 = 0.3f * fast_rcp(d2 * d2);
     return (a0 * q0 + a1 * q1 + a2 * q2) * fast_rcp(6.0f * (a0 + a1 + a2));
+}
+
+// WENO7-JS of a 7-point window v[0..6] (face between v[3] and v[4], upwind
+// side v[0]): four cubic candidates, optimal weights (1, 12, 18, 4)/35,
+// smoothness indicators as the integer quadratic forms (240 x the Jiang-Shu
+// measure), weights C_k/(beta_k+eps)^2 from reciprocals (the indicators can
+// be large, so no common-denominator products).
+template <typename T>
+__device__ __forceinline__ T weno7(const T (&v)[7], T eps) {
+    const T a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5], g = v[6];
+    const T q0 = T(-3) * a + T(13) * b - T(23) * c + T(25) * d;
+    const T q1 = b - T(5) * c + T(13) * d + T(3) * e;
+    const T q2 = -c + T(7) * d + T(7) * e - f;
+    const T q3 = T(3) * d + T(13) * e - T(5) * f + g;
+    T b0 = a * (T(547) * a - T(3882) * b + T(4642) * c - T(1854) * d) +
+           b * (T(7043) * b - T(17246) * c + T(7042) * d) + c * (T(11003) * c - T(9402) * d) +
+           T(2107) * d * d;
+    T b1 = b * (T(267) * b - T(1642) * c + T(1602) * d - T(494) * e) +
+           c * (T(2843) * c - T(5966) * d + T(1922) * e) + d * (T(3443) * d - T(2522) * e) +
+           T(547) * e * e;
+    T b2 = c * (T(547) * c - T(2522) * d + T(1922) * e - T(494) * f) +
+           d * (T(3443) * d - T(5966) * e + T(1602) * f) + e * (T(2843) * e - T(1642) * f) +
+           T(267) * f * f;
+    T b3 = d * (T(2107) * d - T(9402) * e + T(7042) * f - T(1854) * g) +
+           e * (T(11003) * e - T(17246) * f + T(4642) * g) + f * (T(7043) * f - T(3882) * g) +
+           T(547) * g * g;
+    b0 += eps;
+    b1 += eps;
+    b2 += eps;
+    b3 += eps;
+    const T a0 = T(1) * rcp<T>(b0 * b0), a1 = T(12) * rcp<T>(b1 * b1);
+    const T a2 = T(18) * rcp<T>(b2 * b2), a3 = T(4) * rcp<T>(b3 * b3);
+    return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * rcp<T>(T(12) * (a0 + a1 + a2 + a3));
 }
 
 // ---------------------------------------------------------------------------
@@ -452,6 +486,64 @@ __device__ __forceinline__ void face_flux_weno(const LD& ld, const SchemeK& sk,
 }
 
 // ---------------------------------------------------------------------------
+// the face flux: WENO7-JS (Remark 2), stencil nodes i-3 .. i+4 (slots 0..7)
+// ---------------------------------------------------------------------------
+
+template <int DIM, int Y, typename T, class LD>
+__device__ __forceinline__ void face_flux_weno7(const LD& ld, const SchemeK& sk,
+                                                double (&Fo)[DIM + 2]) {
+    constexpr int NV = DIM + 2, E = NV - 1;
+    FaceRef<DIM> R;
+    face_ref<DIM, Y>(ld, sk, R);
+    Eig<DIM, T> S;
+    roe<DIM, T>(ld.after(R.Vf), sk, R, S);
+    T a[NV][8], b[NV][8];
+    T mxm = T(0), mx0 = T(0), mxp = T(0);
+    double chain = double(S.ic);
+#pragma unroll
+    for (int r = 0; r <= 7; ++r) {
+        NodeDiff<DIM, T> N;
+        node_diff<DIM, T>(ld.after(chain), r, sk, R, S, N);
+        chain = N.dQ[0];
+        mxm = fmax(mxm, fabs(N.un - N.cs));
+        mx0 = fmax(mx0, fabs(N.un));
+        mxp = fmax(mxp, fabs(N.un + N.cs));
+        T w[NV], pa[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = T(N.dF[v]);
+        project<DIM, T>(S, w, pa);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a[v][r] = pa[v];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = T(N.dQ[v]);
+        project<DIM, T>(S, w, pa);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) b[v][r] = pa[v];
+    }
+    T lam[NV];
+    lam[0] = S.sigma * mxm;
+#pragma unroll
+    for (int v = 1; v < E; ++v) lam[v] = S.sigma * mx0;
+    lam[E] = S.sigma * mxp;
+    const T eps = T(sk.eps);
+    T h[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T vp[7], vm[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+            vp[r] = T(0.5) * (a[v][r] + lam[v] * b[v][r]);
+            vm[r] = T(0.5) * (a[v][7 - r] - lam[v] * b[v][7 - r]);
+        }
+        h[v] = weno7<T>(vp, eps) + weno7<T>(vm, eps);
+    }
+    T o[NV];
+    backproject<DIM, T>(S, h, o);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fo[v] = R.Fts[v] + double(o[v]);
+}
+
+// ---------------------------------------------------------------------------
 // the face flux: fifth-order linear upwind
 // ---------------------------------------------------------------------------
 // With the optimal weights the two split parts reconstruct linearly, and
@@ -507,6 +599,8 @@ template <int DIM, int RECON, int Y, typename T, class LD>
 __device__ __forceinline__ void face_flux(const LD& ld, const SchemeK& sk, double (&Fo)[DIM + 2]) {
     if constexpr (RECON == 1)
         face_flux_lu5<DIM, Y, T>(ld, sk, Fo);
+    else if constexpr (RECON == 2)
+        face_flux_weno7<DIM, Y, T>(ld, sk, Fo);
     else
         face_flux_weno<DIM, Y, T>(ld, sk, Fo);
 }

@@ -390,24 +390,30 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK s
 
 // LDS of an eta / zeta sweep workgroup: a ring of stencil rows (the q, 1/J
 // and s_DIR values of the workgroup's 64 lines at one node index along
-// DIR) and a double buffer of the four face fluxes of an iteration.
-template <int DIM, int Y>
+// DIR), the four face fluxes of an iteration and the carried last flux of
+// the previous one.
+constexpr int wide_stencil(int recon, int Y) { return (recon == 2 || Y == 8) ? 1 : 0; }
+
+// WIDE: the face reads slots 0..7 (nodes i-3 .. i+4: eighth-order metrics or
+// WENO7), else slots 1..6 (nodes i-2 .. i+3).
+template <int DIM, int WIDE>
 struct WgLds {
     static constexpr int NV = DIM + 2;
     static constexpr int NS = 2 * DIM + 3;   // values per node: q, 1/J, s_DIR
-    static constexpr int LO = Y == 8 ? 3 : 2;  // rows below face i+1/2 read by it: i-LO+1 .. i
-    static constexpr int HI = Y == 8 ? 4 : 3;  // rows above: i+1 .. i+HI
+    static constexpr int LO = WIDE ? 3 : 2;  // nodes below node i a face i+1/2 reads
+    static constexpr int HI = WIDE ? 4 : 3;  // nodes above node i
     static constexpr int WIN = 4 + LO + HI;    // rows read by the four faces of an iteration
     static constexpr int RING = WIN + 4;       // plus the four rows prefetched for the next
     double ring[RING][NS][64];
-    double flux[2][4][NV][64];
+    double flux[4][NV][64];  // the four faces of the current iteration
+    double carry[NV][64];    // the last face of the previous iteration
 };
 
 // Stencil reads of face i+1/2 from the LDS ring: slot r (node i-3+r) is ring
 // row (b0 + r) mod RING.
-template <int DIM, int Y>
+template <int DIM, int WIDE>
 struct LdsLoader {
-    using W = WgLds<DIM, Y>;
+    using W = WgLds<DIM, WIDE>;
     const W* L;
     unsigned la;  // byte offset of this lane in a ring row
     int b0;       // ring row of slot 0, in [0, RING)
@@ -445,8 +451,9 @@ struct LdsLoader {
 template <int DIM, int DIR, int RECON, int Y, int PREC>
 __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
                                               const double* __restrict__ met, const double* qs,
-                                              const EpiK& ep, int S, long item, WgLds<DIM, Y>& L) {
-    using W = WgLds<DIM, Y>;
+                                              const EpiK& ep, int S, long item,
+                                              WgLds<DIM, wide_stencil(RECON, Y)>& L) {
+    using W = WgLds<DIM, wide_stencil(RECON, Y)>;
     constexpr int NV = DIM + 2;
     constexpr int NMET = DIM == 3 ? 10 : 5;
     constexpr int OTH = DIR == 1 ? 2 : 1;
@@ -514,18 +521,17 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = 0.0;
         if (lane_ok && f < k1) {
-            LdsLoader<DIM, Y> ld;
+            LdsLoader<DIM, wide_stencil(RECON, Y)> ld;
             ld.L = &L;
             ld.la = (unsigned)lane * 8u;
             ld.b0 = (f - 3 - tb + W::RING) % W::RING;
             face_flux<DIM, RECON, Y, char_t<PREC>>(ld, sk, F);
         }
-        const int buf = it & 1;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) L.flux[buf][w][v][lane] = F[v];
+        for (int v = 0; v < NV; ++v) L.flux[w][v][lane] = F[v];
         __syncthreads();
         if (mine) {
-            const double* prev = w > 0 ? &L.flux[buf][w - 1][0][0] : &L.flux[buf ^ 1][3][0][0];
+            const double* prev = w > 0 ? &L.flux[w - 1][0][0] : &L.carry[0][0];
             double d[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) d[v] = F[v] - prev[v * 64 + lane];
@@ -536,6 +542,12 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
         }
         __builtin_amdgcn_s_waitcnt(0);  // this wave's row DMA has landed
         __syncthreads();                // every row of the next iteration is in LDS
+        // the next iteration's first face needs this iteration's last flux;
+        // the barrier above ended every read of the carry
+        if (w == 3) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) L.carry[v][lane] = F[v];
+        }
     }
 }
 
@@ -550,7 +562,7 @@ template <int DIM, int DIR, int RECON, int Y, int PREC>
 __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK sk,
                                                                 const double* __restrict__ met,
                                                                 const double* qs, EpiK ep, int S) {
-    __shared__ WgLds<DIM, Y> lds;
+    __shared__ WgLds<DIM, wide_stencil(RECON, Y)> lds;
     sweep_wg_item<DIM, DIR, RECON, Y, PREC>(G, sk, met, qs, ep, S, blockIdx.x, lds);
 }
 
@@ -674,7 +686,7 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_wg(const int* __re
                                                                  const long* __restrict__ t_start,
                                                                  const BBlock* __restrict__ t_blk, int cap,
                                                                  SchemeK sk, int stage) {
-    __shared__ WgLds<DIM, Y> lds;
+    __shared__ WgLds<DIM, wide_stencil(RECON, Y)> lds;
     constexpr int KIND = DIR == 1 ? BK_ETA : BK_ZETA;
     constexpr int MODE = DIR == DIM - 1 ? EPI_LAST_RK : EPI_MID;
     const int nblk = *t_nblk;
