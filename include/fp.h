@@ -168,7 +168,8 @@ fp_status fp_check_state(const fp_grid *grid, const fp_scheme *scheme, const dou
  * with one scheme, by the RK3 step of fp_rk3_step (Sec. 2.2), each block
  * with its own dt.  Per RK stage every sweep direction is ONE persistent
  * launch over a (block, tile) work list of all blocks of a dimensionality;
- * a step is 1 + 3 x ndim such launches, captured once into a HIP graph by
+ * a step is 1 + 3 x (1 + ndim) such launches (ghost copy, then per stage the
+ * interface exchange and the sweeps), captured once into a HIP graph by
  * fp_batch_solve.  Per block the arithmetic is that of fp_rk3_step, and the
  * result is bitwise the same as advancing the block alone.
  *
@@ -207,6 +208,32 @@ fp_status fp_batch_rk3_step(fp_batch *batch, void *stream);
 /* nsteps RK3 steps of every block, replaying the batch's step graph. */
 fp_status fp_batch_solve(fp_batch *batch, int64_t nsteps, void *stream);
 
+/* Multi-block interfaces.  A link makes the ghost layers of `block` on
+ * `side` (0 low, 1 high) of `axis` the interior layers of block `nbr` next
+ * to its opposite side, so that the two blocks form one grid across the
+ * face: the blocks must have the same dimensionality and ghost width, equal
+ * extents and orientation along the other axes, and FP_BC_FROZEN on the
+ * linked axis; an interface shared both ways needs two links.  Every RK
+ * stage then starts with one exchange launch over all links (the stage's
+ * register: q, then the two stage registers), so both blocks evaluate the
+ * same flux on the shared face and the scheme stays conservative across it.
+ * (The multi-block topology the paper's multi-block cases use; a single-GPU
+ * form of the halo exchange a decomposition over GPUs would need.) */
+typedef struct {
+    int32_t block; /* index into the blocks of the last fp_batch_set */
+    int32_t axis;  /* 0 .. ndim-1 */
+    int32_t side;  /* 0: below index 0, 1: above index n-1 */
+    int32_t nbr;   /* the neighbouring block */
+} fp_link;
+
+/* Replaces the batch's links (at most 6 per block slot; fp_batch_set clears
+ * them).  Also copies, once and in stream order, the metric ghost layers of
+ * every linked face from the neighbour's interior metrics: the library
+ * WRITES those ghost layers of the blocks' met arrays.  The state ghost
+ * layers of linked faces (in q and the workspace) are written every step.
+ * Validation as described above; on an error nothing changes. */
+fp_status fp_batch_set_links(fp_batch *batch, const fp_link *links, int32_t nlinks, void *stream);
+
 /* Chooses the eta/zeta segment length of the batch's work list by timing
  * the sweeps of RK stage 1 for a set of candidates on the current blocks
  * (synchronises the stream; the blocks' workspaces are overwritten, q is
@@ -218,9 +245,9 @@ fp_status fp_batch_autotune(fp_batch *batch, int32_t *segment, void *stream);
  * fp_batch_rk3_step, with a HIP event recorded on `stream` after each of its
  * launches; synchronises and writes each launch's duration in milliseconds
  * to kernel_ms[i] and its kind to kernel_kind[i] = 16 * ndim + k (k = 0 xi
- * sweep, 1 eta sweep, 2 zeta sweep, 3 frozen-ghost copy), in launch order,
- * and the number of launches (at most 20) to *n_kernels.  FP_EINVAL if
- * max_kernels is too small (nothing enqueued). */
+ * sweep, 1 eta sweep, 2 zeta sweep, 3 frozen-ghost copy, 4 interface
+ * exchange), in launch order, and the number of launches (at most 26) to
+ * *n_kernels.  FP_EINVAL if max_kernels is too small (nothing enqueued). */
 fp_status fp_batch_profile_step(fp_batch *batch, float *kernel_ms, int32_t *kernel_kind,
                                 int32_t max_kernels, int32_t *n_kernels, void *stream);
 

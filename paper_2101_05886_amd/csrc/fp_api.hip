@@ -300,8 +300,13 @@ struct fp_batch {
     hipEvent_t staged = nullptr;
     bool pending = false;   // a staging copy may still read hstage
     std::vector<fp_block> blocks;
+    std::vector<fp_link> links;  // interfaces, as given (global block indices)
+    int maxl = 0;                // link capacity per part (6 per block)
     int nblk[2] = {0, 0};
     BTab tab[2]{};
+    const int* lnk_n[2] = {nullptr, nullptr};     // device: links per part
+    const long* lnk_start[2] = {nullptr, nullptr}; // device: prefix sums of ghost-slab nodes
+    const LinkK* lnk[2] = {nullptr, nullptr};     // device: the links
     int grid[2][BK_KINDS]{};
     batch_stage_fn fn[2] = {nullptr, nullptr};
     hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};  // by mask of non-empty parts
@@ -312,6 +317,21 @@ namespace {
 
 size_t start_offset() { return 256; }
 size_t blk_offset(int cap) { return 256 + align256(sizeof(long) * BK_KINDS * (size_t)(cap + 1)); }
+// link region of a part: [nlink | 256 B][lstart: maxl + 1 longs][links: maxl]
+size_t lnk_offset(int cap) { return align256(blk_offset(cap) + sizeof(BBlock) * (size_t)cap); }
+size_t lnk_start_offset(int cap) { return lnk_offset(cap) + 256; }
+size_t lnk_arr_offset(int cap, int maxl) {
+    return lnk_start_offset(cap) + align256(sizeof(long) * (size_t)(maxl + 1));
+}
+size_t part_size(int cap, int maxl) { return align256(lnk_arr_offset(cap, maxl) + sizeof(LinkK) * (size_t)maxl); }
+
+// ghost-slab nodes of a link: g layers times the other axes' interior extents
+long link_nodes(const fp_grid& g, int axis) {
+    long c = g.ghost;
+    for (int e = 0; e < g.ndim; ++e)
+        if (e != axis) c *= g.n[e];
+    return c;
+}
 
 int seg_len(int nd, int target) {
     const int nseg = (nd + target - 1) / target;
@@ -319,7 +339,8 @@ int seg_len(int nd, int target) {
 }
 
 // Host image of the tables of both parts for `blocks` (already validated).
-void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, char* img, int nblk[2]) {
+void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, const std::vector<fp_link>& links,
+                  char* img, int nblk[2]) {
     for (int p = 0; p < 2; ++p) {
         char* base = img + p * b->part_bytes;
         long* start = reinterpret_cast<long*>(base + start_offset());
@@ -358,18 +379,40 @@ void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, char* 
         for (int k = 0; k < BK_KINDS; ++k) start[k * (b->cap + 1) + n] = acc[k];
         *reinterpret_cast<int*>(base) = n;
         nblk[p] = n;
+        // the part's links, with block indices local to the part
+        long* lstart = reinterpret_cast<long*>(base + lnk_start_offset(b->cap));
+        LinkK* lk = reinterpret_cast<LinkK*>(base + lnk_arr_offset(b->cap, b->maxl));
+        std::vector<int> local(blocks.size(), -1);
+        int c = 0;
+        for (size_t i = 0; i < blocks.size(); ++i)
+            if (blocks[i].grid.ndim == ndim) local[i] = c++;
+        int nl = 0;
+        long lacc = 0;
+        for (const fp_link& L : links) {
+            if (local[L.block] < 0) continue;
+            lstart[nl] = lacc;
+            lk[nl].a = local[L.block];
+            lk[nl].b = local[L.nbr];
+            lk[nl].axis = L.axis;
+            lk[nl].side = L.side;
+            lacc += link_nodes(blocks[L.block].grid, L.axis);
+            ++nl;
+        }
+        lstart[nl] = lacc;
+        *reinterpret_cast<int*>(base + lnk_offset(b->cap)) = nl;
     }
 }
 
 // Copy the tables of `blocks` to the device in stream order.
-fp_status upload_tables(fp_batch* b, const std::vector<fp_block>& blocks, hipStream_t s) {
+fp_status upload_tables(fp_batch* b, const std::vector<fp_block>& blocks, const std::vector<fp_link>& links,
+                        hipStream_t s) {
     if (b->pending) {
         hipError_t e = hipEventSynchronize(b->staged);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
         b->pending = false;
     }
     int nblk[2];
-    build_tables(b, blocks, b->hstage, nblk);
+    build_tables(b, blocks, links, b->hstage, nblk);
     hipError_t e = hipMemcpyAsync(b->dmem, b->hstage, 2 * b->part_bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch tables)");
     e = hipEventRecord(b->staged, s);
@@ -387,6 +430,8 @@ hipError_t run_batch_step(const fp_batch* b, int mask, hipStream_t s) {
         hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p].nblk,
                            b->tab[p].start, b->tab[p].blk, b->tab[p].cap, ndim);
         for (int k = 0; k < 3; ++k) {
+            hipLaunchKernelGGL(kb_halo, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->lnk_n[p], b->lnk_start[p],
+                               b->lnk[p], b->tab[p].blk, ndim, k);
             hipError_t e = b->fn[p](b->tab[p], b->sk, k, b->grid[p], -1, s);
             if (e != hipSuccess) return e;
         }
@@ -676,7 +721,8 @@ fp_status fp_batch_create(const fp_scheme* sch, int32_t max_blocks, fp_batch** o
     b->sch = *sch;
     b->sk = make_sk(sch);
     b->cap = max_blocks;
-    b->part_bytes = align256(blk_offset(max_blocks) + sizeof(BBlock) * (size_t)max_blocks);
+    b->maxl = 6 * max_blocks;
+    b->part_bytes = part_size(max_blocks, b->maxl);
     hipError_t e = hipGetDevice(&b->dev);
     if (e == hipSuccess) e = hipMalloc((void**)&b->dmem, 2 * b->part_bytes);
     if (e != hipSuccess) {
@@ -706,6 +752,9 @@ fp_status fp_batch_create(const fp_scheme* sch, int32_t max_blocks, fp_batch** o
         b->tab[p].start = reinterpret_cast<const long*>(base + start_offset());
         b->tab[p].blk = reinterpret_cast<const BBlock*>(base + blk_offset(max_blocks));
         b->tab[p].cap = max_blocks;
+        b->lnk_n[p] = reinterpret_cast<const int*>(base + lnk_offset(max_blocks));
+        b->lnk_start[p] = reinterpret_cast<const long*>(base + lnk_start_offset(max_blocks));
+        b->lnk[p] = reinterpret_cast<const LinkK*>(base + lnk_arr_offset(max_blocks, b->maxl));
         b->fn[p] = get_batch_stage_fn(ndim, sch->recon, sch->metric_order, sch->precision);
         batch_occ_fn occ = get_batch_occ_fn(ndim, sch->recon, sch->metric_order, sch->precision);
         if (!b->fn[p] || !occ) {
@@ -737,9 +786,11 @@ fp_status fp_batch_set(fp_batch* b, const fp_block* blocks, int32_t nblocks, voi
         if (!(fb.dt > 0.0)) return fail(FP_EINVAL, "block %d: dt must be positive", i);
     }
     std::vector<fp_block> v(blocks, blocks + nblocks);
-    st = upload_tables(b, v, (hipStream_t)stream);
+    std::vector<fp_link> nolinks;
+    st = upload_tables(b, v, nolinks, (hipStream_t)stream);
     if (st) return st;
     b->blocks.swap(v);
+    b->links.clear();
     return FP_OK;
 }
 
@@ -800,7 +851,7 @@ fp_status fp_batch_autotune(fp_batch* b, int32_t* segment, void* stream) {
     float best_ms = -1.0f;
     for (int T : kSegTargets) {
         b->seg = T;
-        st = upload_tables(b, b->blocks, s);
+        st = upload_tables(b, b->blocks, b->links, s);
         if (st) break;
         float ms = 0.0f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
@@ -824,9 +875,53 @@ fp_status fp_batch_autotune(fp_batch* b, int32_t* segment, void* stream) {
     if (st) return st;
     if (e != hipSuccess) return hip_fail(e, "fp_batch_autotune");
     b->seg = best;
-    st = upload_tables(b, b->blocks, s);
+    st = upload_tables(b, b->blocks, b->links, s);
     if (st) return st;
     if (segment) *segment = best;
+    return FP_OK;
+}
+
+fp_status fp_batch_set_links(fp_batch* b, const fp_link* links, int32_t nlinks, void* stream) {
+    fp_status st = check_batch(b);
+    if (st) return st;
+    const int nb = (int)b->blocks.size();
+    if (nlinks < 0 || nlinks > b->maxl) return fail(FP_EINVAL, "nlinks must be in [0, %d]", b->maxl);
+    if (nlinks > 0 && !links) return fail(FP_EINVAL, "links is NULL");
+    std::vector<char> seen((size_t)nb * 6, 0);
+    for (int i = 0; i < nlinks; ++i) {
+        const fp_link& L = links[i];
+        if (L.block < 0 || L.block >= nb || L.nbr < 0 || L.nbr >= nb)
+            return fail(FP_EINVAL, "link %d: block index out of range", i);
+        const fp_grid& A = b->blocks[L.block].grid;
+        const fp_grid& B = b->blocks[L.nbr].grid;
+        if (A.ndim != B.ndim) return fail(FP_EINVAL, "link %d: blocks of different dimensionality", i);
+        if (L.axis < 0 || L.axis >= A.ndim) return fail(FP_EINVAL, "link %d: axis out of range", i);
+        if (L.side != 0 && L.side != 1) return fail(FP_EINVAL, "link %d: side must be 0 or 1", i);
+        if (A.ghost != B.ghost) return fail(FP_EINVAL, "link %d: blocks of different ghost width", i);
+        if (A.bc[L.axis] != FP_BC_FROZEN || B.bc[L.axis] != FP_BC_FROZEN)
+            return fail(FP_EINVAL, "link %d: linked axes must be FP_BC_FROZEN in both blocks", i);
+        if (B.n[L.axis] < A.ghost) return fail(FP_EINVAL, "link %d: neighbour thinner than the ghost width", i);
+        for (int e = 0; e < A.ndim; ++e)
+            if (e != L.axis && A.n[e] != B.n[e])
+                return fail(FP_EINVAL, "link %d: blocks differ along axis %d", i, e);
+        char& u = seen[(size_t)L.block * 6 + L.axis * 2 + L.side];
+        if (u) return fail(FP_EINVAL, "link %d: face linked twice", i);
+        u = 1;
+    }
+    std::vector<fp_link> v(links, links + nlinks);
+    hipStream_t s = (hipStream_t)stream;
+    st = upload_tables(b, b->blocks, v, s);
+    if (st) return st;
+    b->links.swap(v);
+    // metric ghost layers of the linked faces from the neighbours' interiors,
+    // once: both blocks then see the same metrics at every interface node
+    for (int p = 0; p < 2; ++p) {
+        if (b->nblk[p] == 0) continue;
+        hipLaunchKernelGGL(kb_halo, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->lnk_n[p], b->lnk_start[p],
+                           b->lnk[p], b->tab[p].blk, p == 0 ? 2 : 3, 3);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "fp_batch_set_links launch");
     return FP_OK;
 }
 
@@ -838,17 +933,19 @@ fp_status fp_batch_profile_step(fp_batch* b, float* kernel_ms, int32_t* kernel_k
     hipStream_t s = (hipStream_t)stream;
     const int mask = batch_mask(b);
     // the launches of one step, in order: (part, kind, stage)
-    int plan[2 * 10][3];
+    int plan[2 * 13][3];
     int n = 0;
     for (int p = 0; p < 2; ++p) {
         if (!(mask & (1 << p))) continue;
         const int ndim = p == 0 ? 2 : 3;
         plan[n][0] = p, plan[n][1] = BK_GHOST, plan[n][2] = -1, ++n;
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k) {
+            plan[n][0] = p, plan[n][1] = 4, plan[n][2] = k, ++n;  // interface exchange
             for (int kind = 0; kind < ndim; ++kind) plan[n][0] = p, plan[n][1] = kind, plan[n][2] = k, ++n;
+        }
     }
     if (n > max_kernels) return fail(FP_EINVAL, "max_kernels must be >= %d", n);
-    hipEvent_t ev[2 * 10 + 1];
+    hipEvent_t ev[2 * 13 + 1];
     hipError_t e = hipSuccess;
     int made = 0;
     while (made <= n) {
@@ -862,6 +959,9 @@ fp_status fp_batch_profile_step(fp_batch* b, float* kernel_ms, int32_t* kernel_k
         if (kind == BK_GHOST)
             hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p].nblk,
                                b->tab[p].start, b->tab[p].blk, b->tab[p].cap, p == 0 ? 2 : 3);
+        else if (kind == 4)
+            hipLaunchKernelGGL(kb_halo, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->lnk_n[p],
+                               b->lnk_start[p], b->lnk[p], b->tab[p].blk, p == 0 ? 2 : 3, k);
         else
             e = b->fn[p](b->tab[p], b->sk, k, b->grid[p], kind, s);
         if (e == hipSuccess) e = hipGetLastError();

@@ -585,6 +585,14 @@ struct BBlock {
 // Kinds of work items of a batched RK step.
 enum { BK_X = 0, BK_ETA = 1, BK_ZETA = 2, BK_GHOST = 3, BK_KINDS = 4 };
 
+// An interface between two blocks of a batch: the ghost layers of block a
+// on `side` (0 low, 1 high) of `axis` are the interior layers of block b
+// next to its opposite side (the blocks share the other axes' extents and
+// orientation).
+struct LinkK {
+    int a, b, axis, side;
+};
+
 // Work-item table of a batch, in device memory.  The number of blocks and
 // the prefix sums are read by the kernels at run time, so a captured graph
 // stays valid when the table's contents change:

@@ -208,6 +208,51 @@ __global__ __launch_bounds__(256) void kb_frozen_ghosts(const int* __restrict__ 
     }
 }
 
+// Interface exchange: for every link, the g ghost layers of block a on its
+// side are copied from the interior layers of block b next to the opposite
+// side.  which = 0, 1, 2: the state registers of RK stage 1 (q), 2 (A),
+// 3 (B); which = 3: the metric arrays.  Node t of all links' ghost slabs
+// (prefix sums lstart) per thread; lanes follow their link forward.
+__global__ __launch_bounds__(256) void kb_halo(const int* __restrict__ t_nlink,
+                                               const long* __restrict__ t_lstart,
+                                               const LinkK* __restrict__ t_links,
+                                               const BBlock* __restrict__ t_blk, int ndim, int which) {
+    const int nl = *t_nlink;
+    const long total = t_lstart[nl];
+    int li = 0;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        while (li + 1 < nl && t_lstart[li + 1] <= t) ++li;
+        const LinkK L = t_links[li];
+        const BBlock& A = t_blk[L.a];
+        const BBlock& B = t_blk[L.b];
+        const int g = A.G.g;
+        long u = t - t_lstart[li];
+        const int l = (int)(u % g);
+        u /= g;
+        long oa = A.G.base, ob = B.G.base;
+        for (int e = 0; e < ndim; ++e) {
+            if (e == L.axis) continue;
+            const long c = u % A.G.n[e];
+            u /= A.G.n[e];
+            oa += c * A.G.sd[e];
+            ob += c * B.G.sd[e];
+        }
+        const int ia = L.side ? A.G.n[L.axis] + l : -1 - l;
+        const int ib = L.side ? l : B.G.n[L.axis] - 1 - l;
+        oa += (long)ia * A.G.sd[L.axis];
+        ob += (long)ib * B.G.sd[L.axis];
+        if (which == 3) {
+            double* dst = const_cast<double*>(A.met);
+            const int nmet = ndim == 3 ? 10 : 5;
+            for (int v = 0; v < nmet; ++v) dst[v * A.G.vol + oa] = B.met[v * B.G.vol + ob];
+        } else {
+            double* dst = which == 0 ? A.q : (which == 1 ? A.A : A.B);
+            const double* src = which == 0 ? B.q : (which == 1 ? B.A : B.B);
+            for (int v = 0; v < ndim + 2; ++v) dst[v * A.G.vol + oa] = src[v * B.G.vol + ob];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CFL limit and state check
 // ---------------------------------------------------------------------------

@@ -23,7 +23,7 @@ FP_BC_PERIODIC, FP_BC_FROZEN = 0, 1
 EXPORTS = ["fp_state_bytes", "fp_metric_bytes", "fp_coord_bytes", "fp_work_bytes", "fp_metrics",
            "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve", "fp_max_dt",
            "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step", "fp_batch_solve",
-           "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error"]
+           "fp_batch_set_links", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error"]
 
 
 class FPError(RuntimeError):
@@ -45,6 +45,10 @@ class FPScheme(C.Structure):
 class FPBlock(C.Structure):
     _fields_ = [("grid", FPGrid), ("met", C.c_void_p), ("q", C.c_void_p), ("work", C.c_void_p),
                 ("dt", C.c_double)]
+
+
+class FPLink(C.Structure):
+    _fields_ = [("block", C.c_int32), ("axis", C.c_int32), ("side", C.c_int32), ("nbr", C.c_int32)]
 
 
 _lib = None
@@ -75,6 +79,7 @@ def lib():
         L.fp_batch_create.argtypes = [sp, C.c_int32, C.POINTER(C.c_void_p)]
         L.fp_batch_set.argtypes = [bp, C.POINTER(FPBlock), C.c_int32, vp]
         L.fp_batch_rk3_step.argtypes = [bp, vp]
+        L.fp_batch_set_links.argtypes = [bp, C.POINTER(FPLink), C.c_int32, vp]
         L.fp_batch_solve.argtypes = [bp, C.c_int64, vp]
         L.fp_batch_autotune.argtypes = [bp, C.POINTER(C.c_int32), vp]
         L.fp_batch_profile_step.argtypes = [bp, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32,
@@ -86,7 +91,7 @@ def lib():
         L.fp_last_error.restype = C.c_char_p
         for name in ("fp_metrics", "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve",
                      "fp_max_dt", "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step",
-                     "fp_batch_solve", "fp_batch_autotune", "fp_batch_profile_step"):
+                     "fp_batch_solve", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_set_links"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -301,6 +306,14 @@ class Batch:
         _check(lib().fp_batch_set(self._h, arr, len(blocks), _stream()))
         self._keep = keep
 
+    def set_links(self, links):
+        """links: (block, axis, side, nbr) tuples (see fp_batch_set_links);
+        interfaces shared both ways need both directions."""
+        arr = (FPLink * max(1, len(links)))()
+        for i, (blk, axis, side, nbr) in enumerate(links):
+            arr[i].block, arr[i].axis, arr[i].side, arr[i].nbr = int(blk), int(axis), int(side), int(nbr)
+        _check(lib().fp_batch_set_links(self._h, arr, len(links), _stream()))
+
     def rk3_step(self):
         _check(lib().fp_batch_rk3_step(self._h, _stream()))
 
@@ -314,7 +327,8 @@ class Batch:
 
     def profile_step(self):
         """One RK3 step with per-launch HIP-event timing: [(ndim, kind, ms)]
-        in launch order, kind 0/1/2 = xi/eta/zeta sweep, 3 = ghost copy."""
+        in launch order, kind 0/1/2 = xi/eta/zeta sweep, 3 = ghost copy,
+        4 = interface exchange."""
         ms = (C.c_float * 32)()
         kinds = (C.c_int32 * 32)()
         n = C.c_int32(0)
