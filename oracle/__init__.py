@@ -71,6 +71,10 @@ def lib():
         L.fpo_weno7.restype = C.c_double
         L.fpo_weno7_parts.argtypes = [dp, dp, dp]
         L.fpo_weno7_parts.restype = None
+        L.fpo_wenocu6.argtypes = [dp, C.c_double]
+        L.fpo_wenocu6.restype = C.c_double
+        L.fpo_wenocu6_parts.argtypes = [dp, dp, dp]
+        L.fpo_wenocu6_parts.restype = None
         L.fpo_face_interp.argtypes = [C.c_int, dp]
         L.fpo_face_interp.restype = C.c_double
         L.fpo_eigensystem.argtypes = [C.c_int, C.c_double, dp, dp, dp, C.c_double, dp, dp, dp]
@@ -132,7 +136,7 @@ class Grid:
 
 class Scheme:
     def __init__(self, recon="weno5", Y=6, reformulated=True, gamma=1.4, eps=1e-6):
-        self.recon = {"weno5": 0, "linup5": 1, "weno7": 2}[recon] if isinstance(recon, str) else int(recon)
+        self.recon = {"weno5": 0, "linup5": 1, "weno7": 2, "wenocu6": 3}[recon] if isinstance(recon, str) else int(recon)
         self.Y, self.reformulated, self.gamma, self.eps = int(Y), bool(reformulated), gamma, eps
 
     def c(self):
@@ -240,6 +244,19 @@ def weno7_parts(v):
     v = _arr(v)
     q, b = np.zeros(4), np.zeros(4)
     lib().fpo_weno7_parts(_dp(v), _dp(q), _dp(b))
+    return q, b
+
+
+def wenocu6(v, eps=1e-6) -> float:
+    v = _arr(v)
+    return float(lib().fpo_wenocu6(_dp(v), eps))
+
+
+def wenocu6_parts(v):
+    """(candidate face values q[4], smoothness measures beta[4], beta[3] = beta6)"""
+    v = _arr(v)
+    q, b = np.zeros(4), np.zeros(4)
+    lib().fpo_wenocu6_parts(_dp(v), _dp(q), _dp(b))
     return q, b
 
 

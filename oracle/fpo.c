@@ -591,15 +591,131 @@ double fpo_weno7(const double v[7], double eps)
     return out;
 }
 
+/* The polynomial p(x) = sum_k c[k] x^k of degree n-1 whose averages over the
+ * unit cells [m-1/2, m+1/2], m = m0 .. m0+n-1, are f[0..n-1] (x measured from
+ * the centre of the cell left of the face, unit spacing): the cell-average
+ * reconstruction behind every WENO candidate.  Gaussian elimination with
+ * partial pivoting, n <= 6. */
+static void cellavg_poly(int n, int m0, const double *f, double *c)
+{
+    double A[6][7];
+    for (int r = 0; r < n; r++) {
+        double lo = m0 + r - 0.5, hi = m0 + r + 0.5;
+        for (int k = 0; k < n; k++)
+            A[r][k] = (pow(hi, k + 1) - pow(lo, k + 1)) / (k + 1);
+        A[r][n] = f[r];
+    }
+    for (int col = 0; col < n; col++) {
+        int piv = col;
+        for (int r = col + 1; r < n; r++)
+            if (fabs(A[r][col]) > fabs(A[piv][col]))
+                piv = r;
+        for (int k = 0; k <= n; k++) {
+            double t = A[col][k];
+            A[col][k] = A[piv][k];
+            A[piv][k] = t;
+        }
+        for (int r = col + 1; r < n; r++) {
+            double fac = A[r][col] / A[col][col];
+            for (int k = col; k <= n; k++)
+                A[r][k] -= fac * A[col][k];
+        }
+    }
+    for (int r = n - 1; r >= 0; r--) {
+        double s = A[r][n];
+        for (int k = r + 1; k < n; k++)
+            s -= A[r][k] * c[k];
+        c[r] = s / A[r][r];
+    }
+}
+
+static double poly_at(int n, const double *c, double x)
+{
+    double s = 0.0;
+    for (int k = n - 1; k >= 0; k--)
+        s = s * x + c[k];
+    return s;
+}
+
+/* smoothness of a candidate in the Jiang-Shu sense at unit spacing:
+ * sum_{l=1}^{n-1} int_{-1/2}^{1/2} (p^(l)(x))^2 dx over the cell left of the
+ * face */
+static double smoothness(int n, const double *c)
+{
+    double d[6], tot = 0.0;
+    for (int k = 0; k < n; k++)
+        d[k] = c[k];
+    for (int l = 1; l < n; l++) {
+        int m = n - l; /* terms of the l-th derivative */
+        for (int k = 0; k < m; k++)
+            d[k] = (k + 1) * d[k + 1];
+        for (int a = 0; a < m; a++)
+            for (int b = 0; b < m; b++)
+                if ((a + b) % 2 == 0)
+                    tot += d[a] * d[b] * 2.0 * pow(0.5, a + b + 1) / (a + b + 1);
+    }
+    return tot;
+}
+
+/* WENOCU6, the sixth-order adaptive central-upwind WENO the paper extends its
+ * method to (Remark 2; Hu, Wang and Adams 2010): v = (f_{i-2} .. f_{i+3}),
+ * the face i+1/2.  Candidates: the quadratic cell-average reconstructions on
+ * {i-2..i}, {i-1..i+1}, {i..i+2} and the downwind {i+1..i+3}, evaluated at the
+ * face; optimal weights (1, 9, 9, 1)/20 (together the sixth-order central
+ * interpolation).  Smoothness: the Jiang-Shu measure of the three upwind
+ * candidates, and for the downwind slot the measure beta6 of the quintic
+ * reconstruction over all six cells, both integrated over cell i.  Weights
+ * alpha_k = d_k (C + tau6/(beta_k + eps))^q with
+ * tau6 = beta6 - (beta_0 + 4 beta_1 + beta_2)/6, C = 20, q = 2 (the cited
+ * scheme's constants; the paper gives none) and the caller's eps (the paper's
+ * WENO epsilon, 1e-6).  Everything here comes from the definitions:
+ * reconstruct, evaluate, integrate. */
+void fpo_wenocu6_parts(const double v[6], double q[4], double beta[4])
+{
+    double c[6];
+    for (int k = 0; k < 4; k++) {
+        cellavg_poly(3, k - 2, v + k, c);
+        q[k] = poly_at(3, c, 0.5);
+        beta[k] = smoothness(3, c);
+    }
+    cellavg_poly(6, -2, v, c);
+    beta[3] = smoothness(6, c);
+}
+
+double fpo_wenocu6(const double v[6], double eps)
+{
+    const double d[4] = {1.0 / 20.0, 9.0 / 20.0, 9.0 / 20.0, 1.0 / 20.0};
+    const double C = 20.0, qexp = 2.0;
+    double q[4], beta[4], alpha[4], asum = 0.0, out = 0.0;
+    fpo_wenocu6_parts(v, q, beta);
+    double tau6 = beta[3] - (beta[0] + 4.0 * beta[1] + beta[2]) / 6.0;
+    for (int k = 0; k < 4; k++) {
+        alpha[k] = d[k] * pow(C + tau6 / (beta[k] + eps), qexp);
+        asum += alpha[k];
+    }
+    for (int k = 0; k < 4; k++)
+        out += alpha[k] / asum * q[k];
+    return out;
+}
+
 /* half-width of the split-flux stencil below the face node i: the "+" part
- * uses f_{i-lo} .. f_{i+lo}, the "-" part f_{i+lo+1} .. f_{i-lo+1} */
+ * uses f_{i-lo} .. f_{i+lo} (WENOCU6: .. f_{i+lo+1}), the "-" part
+ * f_{i+lo+1} .. f_{i-lo+1} (WENOCU6: .. f_{i-lo}) */
 static int stencil_lo(const fpo_scheme *sc)
 {
     return sc->recon == 2 ? 3 : 2;
 }
 
+/* values a reconstruction takes from the split-flux stencil of 2 lo + 2 */
+static int recon_width(const fpo_scheme *sc)
+{
+    return sc->recon == 3 ? 2 * stencil_lo(sc) + 2 : 2 * stencil_lo(sc) + 1;
+}
+
 static double reconstruct(const fpo_scheme *sc, const double *v)
 {
+    if (sc->recon == 3)
+        return fpo_wenocu6(v, sc->eps);
     if (sc->recon == 2)
         return fpo_weno7(v, sc->eps);
     return sc->recon == 1 ? fpo_linear_upwind5(v) : fpo_weno5(v, sc->eps);
@@ -722,11 +838,13 @@ static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, double *Fp)
         }
 
     /* (7) reconstruction of both split parts at the face: the "+" part from
-     * m = i-lo .. i+lo, the "-" part mirrored from m = i+lo+1 .. i-lo+1 */
+     * m = i-lo .. i+lo, the "-" part mirrored from m = i+lo+1 .. i-lo+1
+     * (WENOCU6 takes the whole stencil in both orientations) */
     double hp[NVMAX], hm[NVMAX];
+    const int nr = recon_width(sc);
     for (int s = 0; s < nv; s++) {
-        double a[7], b[7];
-        for (int r = 0; r < ns - 1; r++) {
+        double a[8], b[8];
+        for (int r = 0; r < nr; r++) {
             a[r] = vp[s][r];
             b[r] = vm[s][ns - 1 - r];
         }
@@ -800,7 +918,7 @@ static void gather_line(const layout *L, const double *q, const double *met, int
 
 static int check_scheme(const layout *L, const fpo_scheme *sc)
 {
-    if (!sc || sc->recon < 0 || sc->recon > 2 || (sc->reformulated != 0 && sc->reformulated != 1))
+    if (!sc || sc->recon < 0 || sc->recon > 3 || (sc->reformulated != 0 && sc->reformulated != 1))
         return -1;
     if (sc->Y != 2 && sc->Y != 4 && sc->Y != 6 && sc->Y != 8)
         return -1;

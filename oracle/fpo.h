@@ -37,7 +37,7 @@ typedef struct {
 } fpo_grid;
 
 typedef struct {
-    int recon;         /* 0: WENO5-JS, 1: fifth-order linear upwind, 2: WENO7-JS */
+    int recon;         /* 0: WENO5-JS, 1: fifth-order linear upwind, 2: WENO7-JS, 3: WENOCU6 */
     int Y;             /* metric order 2, 4, 6, 8 */
     int reformulated;  /* 1: the paper's method; 0: standard scheme (Q* = 0) */
     double gamma;      /* ratio of specific heats */
@@ -87,6 +87,9 @@ double fpo_linear_upwind5(const double v[5]);          /* eq. (linear_upwind) */
 double fpo_weno7(const double v[7], double eps);       /* WENO7-JS (Remark 2) */
 /* its four candidate face values q[k] and smoothness indicators beta[k] */
 void fpo_weno7_parts(const double v[7], double q[4], double beta[4]);
+double fpo_wenocu6(const double v[6], double eps);     /* WENOCU6 (Remark 2) */
+/* its candidate face values and smoothness measures (beta[3] = beta6) */
+void fpo_wenocu6_parts(const double v[6], double q[4], double beta[4]);
 double fpo_face_interp(int Y, const double *w);        /* eq. (metric_discret) */
 int fpo_eigensystem(int ndim, double gamma, const double *qL, const double *qR,
                     const double *sf, double Vf, double *L, double *R, double *lam);
