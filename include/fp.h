@@ -65,7 +65,11 @@ typedef enum {
     FP_ENONPHYS = -5       /* reserved for state checks reported to the host */
 } fp_status;
 
-enum { FP_WENO5JS = 0, FP_LINUP5 = 1, FP_WENO7JS = 2 };  /* reconstruction */
+/* Reconstruction of the characteristic split fluxes (Sec. 3 and Remark 2):
+ * WENO5-JS and the fifth-order linear upwind scheme (ghost >= 3), WENO7-JS
+ * (ghost >= 4) and WENOCU6, the sixth-order adaptive central-upwind WENO
+ * (ghost >= 3; C = 20, q = 2; in FP_MIXED32 its epsilon is floored at 1e-30). */
+enum { FP_WENO5JS = 0, FP_LINUP5 = 1, FP_WENO7JS = 2, FP_WENOCU6 = 3 };
 enum { FP_FP64 = 0, FP_MIXED32 = 1 };            /* precision of the characteristic part */
 enum { FP_BC_PERIODIC = 0, FP_BC_FROZEN = 1 };   /* per axis */
 
@@ -93,7 +97,7 @@ typedef struct {
     int32_t reformulated;
     int32_t precision;
     double gamma;     /* ratio of specific heats, > 1 (the paper: 1.4) */
-    double weno_eps;  /* WENO epsilon, > 0 (the paper: 1e-6) */
+    double weno_eps;  /* WENO epsilon, > 0 (the paper: 1e-6, for every WENO scheme) */
 } fp_scheme;
 
 /* Sizes in bytes of the caller-allocated arrays. */

@@ -27,6 +27,8 @@ UNITS = [("fp_inst.hip", ["-DFP_INST_PREC=0", "-DFP_INST_RECON=0"], "inst_p0_r0.
          ("fp_inst.hip", ["-DFP_INST_PREC=1", "-DFP_INST_RECON=1"], "inst_p1_r1.o"),
          ("fp_inst.hip", ["-DFP_INST_PREC=0", "-DFP_INST_RECON=2"], "inst_p0_r2.o"),
          ("fp_inst.hip", ["-DFP_INST_PREC=1", "-DFP_INST_RECON=2"], "inst_p1_r2.o"),
+         ("fp_inst.hip", ["-DFP_INST_PREC=0", "-DFP_INST_RECON=3"], "inst_p0_r3.o"),
+         ("fp_inst.hip", ["-DFP_INST_PREC=1", "-DFP_INST_RECON=3"], "inst_p1_r3.o"),
          ("fp_api.hip", [], "api.o")]
 
 

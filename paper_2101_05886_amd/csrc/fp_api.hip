@@ -27,35 +27,44 @@ namespace fpk {
 FP_DECL_GET(0, 0)
 FP_DECL_GET(0, 1)
 FP_DECL_GET(0, 2)
+FP_DECL_GET(0, 3)
 FP_DECL_GET(1, 0)
 FP_DECL_GET(1, 1)
 FP_DECL_GET(1, 2)
+FP_DECL_GET(1, 3)
 #undef FP_DECL_GET
 
+// the instantiation of one (precision, reconstruction) pair
+#define FP_PICK(name, prec, recon, ...)                                                        \
+    ((prec) == 0 ? ((recon) == 0   ? name##_p0_r0(__VA_ARGS__)                                 \
+                    : (recon) == 1 ? name##_p0_r1(__VA_ARGS__)                                 \
+                    : (recon) == 2 ? name##_p0_r2(__VA_ARGS__)                                 \
+                                   : name##_p0_r3(__VA_ARGS__))                                \
+                 : ((recon) == 0   ? name##_p1_r0(__VA_ARGS__)                                 \
+                    : (recon) == 1 ? name##_p1_r1(__VA_ARGS__)                                 \
+                    : (recon) == 2 ? name##_p1_r2(__VA_ARGS__)                                 \
+                                   : name##_p1_r3(__VA_ARGS__)))
+
 stage_fn get_stage_fn(int ndim, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_stage_p0_r0(ndim, Y) : recon == 1 ? get_stage_p0_r1(ndim, Y) : get_stage_p0_r2(ndim, Y);
-    return recon == 0 ? get_stage_p1_r0(ndim, Y) : recon == 1 ? get_stage_p1_r1(ndim, Y) : get_stage_p1_r2(ndim, Y);
+    return FP_PICK(get_stage, prec, recon, ndim, Y);
 }
 
 dir_fn get_dir_fn(int ndim, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_dir_p0_r0(ndim, Y) : recon == 1 ? get_dir_p0_r1(ndim, Y) : get_dir_p0_r2(ndim, Y);
-    return recon == 0 ? get_dir_p1_r0(ndim, Y) : recon == 1 ? get_dir_p1_r1(ndim, Y) : get_dir_p1_r2(ndim, Y);
+    return FP_PICK(get_dir, prec, recon, ndim, Y);
 }
 
 batch_stage_fn get_batch_stage_fn(int ndim, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_batch_stage_p0_r0(ndim, Y) : recon == 1 ? get_batch_stage_p0_r1(ndim, Y) : get_batch_stage_p0_r2(ndim, Y);
-    return recon == 0 ? get_batch_stage_p1_r0(ndim, Y) : recon == 1 ? get_batch_stage_p1_r1(ndim, Y) : get_batch_stage_p1_r2(ndim, Y);
+    return FP_PICK(get_batch_stage, prec, recon, ndim, Y);
 }
 
 batch_occ_fn get_batch_occ_fn(int ndim, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_batch_occ_p0_r0(ndim, Y) : recon == 1 ? get_batch_occ_p0_r1(ndim, Y) : get_batch_occ_p0_r2(ndim, Y);
-    return recon == 0 ? get_batch_occ_p1_r0(ndim, Y) : recon == 1 ? get_batch_occ_p1_r1(ndim, Y) : get_batch_occ_p1_r2(ndim, Y);
+    return FP_PICK(get_batch_occ, prec, recon, ndim, Y);
 }
 
 faceflux_fn get_faceflux_fn(int ndim, int dir, int recon, int Y, int prec) {
-    if (prec == 0) return recon == 0 ? get_faceflux_p0_r0(ndim, dir, Y) : recon == 1 ? get_faceflux_p0_r1(ndim, dir, Y) : get_faceflux_p0_r2(ndim, dir, Y);
-    return recon == 0 ? get_faceflux_p1_r0(ndim, dir, Y) : recon == 1 ? get_faceflux_p1_r1(ndim, dir, Y) : get_faceflux_p1_r2(ndim, dir, Y);
+    return FP_PICK(get_faceflux, prec, recon, ndim, dir, Y);
 }
+#undef FP_PICK
 
 }  // namespace fpk
 
@@ -100,7 +109,7 @@ fp_status check_grid(const fp_grid* g) {
 
 fp_status check_scheme(const fp_grid* g, const fp_scheme* s) {
     if (!s) return fail(FP_EINVAL, "scheme is NULL");
-    if (s->recon != FP_WENO5JS && s->recon != FP_LINUP5 && s->recon != FP_WENO7JS)
+    if (s->recon != FP_WENO5JS && s->recon != FP_LINUP5 && s->recon != FP_WENO7JS && s->recon != FP_WENOCU6)
         return fail(FP_EINVAL, "unknown recon %d", s->recon);
     const int Y = s->metric_order;
     if (Y != 2 && Y != 4 && Y != 6 && Y != 8)

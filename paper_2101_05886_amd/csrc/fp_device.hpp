@@ -176,6 +176,55 @@ __device__ __forceinline__ T weno7(const T (&v)[7], T eps) {
     return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * rcp<T>(T(12) * (a0 + a1 + a2 + a3));
 }
 
+// WENOCU6 (the adaptive central-upwind sixth-order WENO of Hu, Wang and Adams,
+// Remark 2) of a 6-point window v[0..5] = f_{i-2} .. f_{i+3}, the face between
+// v[2] and v[3].  Candidates: the three upwind quadratics of WENO5 and the
+// downwind one on {i+1, i+2, i+3}; optimal weights (1, 9, 9, 1)/20 (the
+// sixth-order central interpolation).  The downwind slot's indicator is beta6,
+// the Jiang-Shu measure (derivative orders 1..5 over cell i) of the quintic
+// through all six cell averages, evaluated from the quintic's Taylor
+// coefficients D_l = p^(l) at the centre of cell i: each D_l is a difference
+// stencil (its coefficients sum to zero), so beta6 keeps its accuracy in FP32,
+// where the expanded integer quadratic form of the six values cancels to
+// noise.  Weights alpha_k = d_k (C + tau6/(beta_k + eps))^2, C = 20,
+// tau6 = beta6 - (beta_0 + 4 beta_1 + beta_2)/6, evaluated as
+// ((C m + tau6 m/(beta_k+eps)) / (m + |tau6|))^2 with m = min_k (beta_k+eps):
+// the same ratios, every factor in [-C, C], so no overflow for any eps.
+template <typename T>
+__device__ __forceinline__ T wenocu6(const T (&v)[6], T eps) {
+    const T a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5];
+    const T q0 = T(2) * a - T(7) * b + T(11) * c;
+    const T q1 = -b + T(5) * c + T(2) * d;
+    const T q2 = T(2) * c + T(5) * d - e;
+    const T q3 = T(11) * d - T(7) * e + T(2) * f;
+    const T t0 = a - T(2) * b + c, s0 = a - T(4) * b + T(3) * c;
+    const T t1 = b - T(2) * c + d, s1 = d - b;
+    const T t2 = c - T(2) * d + e, s2 = T(3) * c - T(4) * d + e;
+    const T k13 = T(13.0 / 12.0);
+    const T b0 = k13 * t0 * t0 + T(0.25) * s0 * s0;
+    const T b1 = k13 * t1 * t1 + T(0.25) * s1 * s1;
+    const T b2 = k13 * t2 * t2 + T(0.25) * s2 * s2;
+    const T D1 = (T(341) * a - T(2785) * b - T(2590) * c + T(6670) * d - T(1895) * e + T(259) * f) *
+                 T(1.0 / 5760.0);
+    const T D2 = (-a + T(12) * b - T(22) * c + T(12) * d - e) * T(0.125);
+    const T D3 = (T(-5) * a - T(11) * b + T(70) * c - T(94) * d + T(47) * e - T(7) * f) * T(1.0 / 24.0);
+    const T D4 = a - T(4) * b + T(6) * c - T(4) * d + e;
+    const T D5 = -a + T(5) * b - T(10) * c + T(10) * d - T(5) * e + f;
+    const T b6 = D1 * (D1 + D3 * T(1.0 / 12.0) + D5 * T(1.0 / 960.0)) +
+                 D2 * (D2 * T(13.0 / 12.0) + D4 * T(7.0 / 80.0)) +
+                 D3 * (D3 * T(1043.0 / 960.0) + D5 * T(4709.0 / 53760.0)) +
+                 D4 * D4 * T(87617.0 / 80640.0) + D5 * D5 * T(50467427.0 / 46448640.0);
+    const T tau = b6 - (b0 + T(4) * b1 + b2) * T(1.0 / 6.0);
+    const T e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps, e3 = b6 + eps;
+    const T m = fmin(fmin(e0, e1), fmin(e2, e3));
+    const T ig = rcp<T>(m + fabs(tau));
+    const T sC = T(20) * (m * ig), st = tau * ig;
+    const T w0 = sC + st * (m * rcp<T>(e0)), w1 = sC + st * (m * rcp<T>(e1));
+    const T w2 = sC + st * (m * rcp<T>(e2)), w3 = sC + st * (m * rcp<T>(e3));
+    const T a0 = w0 * w0, a1 = T(9) * (w1 * w1), a2 = T(9) * (w2 * w2), a3 = w3 * w3;
+    return (a0 * q0 + a1 * q1 + a2 * q2 + a3 * q3) * rcp<T>(T(6) * (a0 + a1 + a2 + a3));
+}
+
 // ---------------------------------------------------------------------------
 // phase A: cell-face reference state
 // ---------------------------------------------------------------------------
@@ -425,10 +474,10 @@ __device__ __forceinline__ void backproject(const Eig<DIM, T>& S, const T (&h)[D
 }
 
 // ---------------------------------------------------------------------------
-// the face flux: WENO5-JS
+// the face flux: WENO5-JS and WENOCU6 (stencil nodes i-2 .. i+3, slots 1..6)
 // ---------------------------------------------------------------------------
 
-template <int DIM, int Y, typename T, class LD>
+template <int DIM, int Y, typename T, bool CU6, class LD>
 __device__ __forceinline__ void face_flux_weno(const LD& ld, const SchemeK& sk,
                                                double (&Fo)[DIM + 2]) {
     constexpr int NV = DIM + 2, E = NV - 1;
@@ -466,7 +515,9 @@ __device__ __forceinline__ void face_flux_weno(const LD& ld, const SchemeK& sk,
 #pragma unroll
     for (int v = 1; v < E; ++v) lam[v] = S.sigma * mx0;
     lam[E] = S.sigma * mxp;
-    const T eps = T(sk.eps);
+    // WENOCU6's eps may be far below the FP32 normal range (1e-40 in the
+    // published scheme): the FP32 path floors it at 1e-30
+    const T eps = (CU6 && sizeof(T) == 4) ? fmax(T(sk.eps), T(1e-30)) : T(sk.eps);
     T h[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -474,10 +525,13 @@ __device__ __forceinline__ void face_flux_weno(const LD& ld, const SchemeK& sk,
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
             vp[r] = T(0.5) * (a[v][r] + lam[v] * b[v][r]);
-            vm[r] = T(0.5) * (a[v][r] - lam[v] * b[v][r]);
+            vm[r] = T(0.5) * (a[v][5 - r] - lam[v] * b[v][5 - r]);
         }
-        h[v] = weno5(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
-               weno5(vm[5], vm[4], vm[3], vm[2], vm[1], eps);
+        if constexpr (CU6)
+            h[v] = wenocu6<T>(vp, eps) + wenocu6<T>(vm, eps);
+        else
+            h[v] = weno5(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
+                   weno5(vm[0], vm[1], vm[2], vm[3], vm[4], eps);
     }
     T o[NV];
     backproject<DIM, T>(S, h, o);
@@ -602,7 +656,7 @@ __device__ __forceinline__ void face_flux(const LD& ld, const SchemeK& sk, doubl
     else if constexpr (RECON == 2)
         face_flux_weno7<DIM, Y, T>(ld, sk, Fo);
     else
-        face_flux_weno<DIM, Y, T>(ld, sk, Fo);
+        face_flux_weno<DIM, Y, T, RECON == 3>(ld, sk, Fo);
 }
 
 }  // namespace fpk

@@ -1,7 +1,7 @@
 // fp_inst.hip -- instantiates the sweep and face-flux kernels for one
 // (precision, reconstruction) pair, selected at compile time by FP_INST_PREC
 // (0 = FP64, 1 = mixed FP32) and FP_INST_RECON (0 = WENO5-JS, 1 = linear
-// upwind, 2 = WENO7-JS).  The build compiles this file once per pair, in parallel.
+// upwind, 2 = WENO7-JS, 3 = WENOCU6).  The build compiles this file once per pair, in parallel.
 #include "fp_kernels.hpp"
 
 #if !defined(FP_INST_PREC) || !defined(FP_INST_RECON)

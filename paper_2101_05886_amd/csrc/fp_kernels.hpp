@@ -512,7 +512,7 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
         // this wave's node f: its epilogue operands load while the face is
         // computed, unless the face computation needs every register (WENO
         // in FP64)
-        constexpr bool early = !(RECON == 0 && PREC == 0);
+        constexpr bool early = !((RECON == 0 || RECON == 3) && PREC == 0);
         const bool mine = lane_ok && f >= k0 && f < k1;
         const long noff = lb + (long)f * G.sd[DIR];
         EpiPre<NV> pre;

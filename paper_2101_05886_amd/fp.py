@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfp.so")
 
 FP_OK, FP_EINVAL, FP_EUNSUPPORTED, FP_EHIP, FP_ENOMEM, FP_ENONPHYS = 0, -1, -2, -3, -4, -5
-FP_WENO5JS, FP_LINUP5, FP_WENO7JS = 0, 1, 2
+FP_WENO5JS, FP_LINUP5, FP_WENO7JS, FP_WENOCU6 = 0, 1, 2, 3
 FP_FP64, FP_MIXED32 = 0, 1
 FP_BC_PERIODIC, FP_BC_FROZEN = 0, 1
 
@@ -151,7 +151,8 @@ class Grid:
 class Scheme:
     def __init__(self, recon="weno5", metric_order=6, reformulated=True, precision="fp64",
                  gamma=1.4, weno_eps=1e-6):
-        self.recon = {"weno5": FP_WENO5JS, "linup5": FP_LINUP5, "weno7": FP_WENO7JS}.get(recon, recon)
+        self.recon = {"weno5": FP_WENO5JS, "linup5": FP_LINUP5, "weno7": FP_WENO7JS,
+                      "wenocu6": FP_WENOCU6}.get(recon, recon)
         self.precision = {"fp64": FP_FP64, "mixed": FP_MIXED32}.get(precision, precision)
         self.metric_order, self.reformulated = int(metric_order), int(bool(reformulated))
         self.gamma, self.weno_eps = float(gamma), float(weno_eps)
