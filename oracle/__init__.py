@@ -37,7 +37,14 @@ class _Grid(C.Structure):
 
 class _Scheme(C.Structure):
     _fields_ = [("recon", C.c_int), ("Y", C.c_int), ("reformulated", C.c_int),
-                ("gamma", C.c_double), ("eps", C.c_double)]
+                ("gamma", C.c_double), ("eps", C.c_double), ("splitting", C.c_int),
+                ("mu", C.c_double), ("prandtl", C.c_double)]
+
+
+class _Bcs(C.Structure):
+    _fields_ = [("kind", (C.c_int * 2) * 3), ("mask", (C.c_void_p * 2) * 3), ("nodes", C.c_void_p),
+                ("pre", C.c_double * 5), ("post", C.c_double * 5), ("normal", C.c_double * 3),
+                ("offset", C.c_double), ("speed", C.c_double)]
 
 
 _lib = None
@@ -61,6 +68,10 @@ def lib():
         L.fpo_residual_at_xyz.argtypes = [gp, sp, dp, dp, C.c_int, ip, dp]
         L.fpo_rk3_step.argtypes = [gp, sp, dp, dp, C.c_double]
         L.fpo_solve.argtypes = [gp, sp, dp, dp, C.c_double, C.c_long]
+        bp = C.POINTER(_Bcs)
+        L.fpo_apply_bcs.argtypes = [gp, bp, dp, dp, C.c_double]
+        L.fpo_solve_bcs.argtypes = [gp, sp, bp, dp, dp, C.c_double, C.c_double, C.c_long]
+        L.fpo_glf_speeds.argtypes = [gp, sp, dp, dp, C.c_int, dp]
         L.fpo_max_dt.argtypes = [gp, sp, dp, dp, C.c_double]
         L.fpo_max_dt.restype = C.c_double
         L.fpo_weno5.argtypes = [dp, C.c_double]
@@ -135,15 +146,59 @@ class Grid:
 
 
 class Scheme:
-    def __init__(self, recon="weno5", Y=6, reformulated=True, gamma=1.4, eps=1e-6):
+    def __init__(self, recon="weno5", Y=6, reformulated=True, gamma=1.4, eps=1e-6, splitting="llf",
+                 mu=0.0, prandtl=0.72):
         self.recon = {"weno5": 0, "linup5": 1, "weno7": 2, "wenocu6": 3}[recon] if isinstance(recon, str) else int(recon)
         self.Y, self.reformulated, self.gamma, self.eps = int(Y), bool(reformulated), gamma, eps
+        self.splitting = {"llf": 0, "glf": 1}[splitting] if isinstance(splitting, str) else int(splitting)
+        self.mu, self.prandtl = float(mu), float(prandtl)
 
     def c(self):
         s = _Scheme()
         s.recon, s.Y, s.reformulated = self.recon, self.Y, int(self.reformulated)
-        s.gamma, s.eps = self.gamma, self.eps
+        s.gamma, s.eps, s.splitting = self.gamma, self.eps, self.splitting
+        s.mu, s.prandtl = self.mu, self.prandtl
         return s
+
+
+HOLD, EXTRAP, WALL, SHOCK = 0, 1, 2, 3
+
+
+class Bcs:
+    """boundary faces: kind[axis][side] in HOLD / EXTRAP / WALL / SHOCK, an
+    optional byte mask per face (1 = the kind applies, 0 = hold), the state
+    nodes' coordinates for SHOCK, and the shock's states and plane"""
+
+    def __init__(self, kind, mask=None, nodes=None, pre=None, post=None, normal=(1.0, 0.0, 0.0),
+                 offset=0.0, speed=0.0):
+        self.kind = [list(k) for k in kind] + [[0, 0]] * (3 - len(kind))
+        self.mask = mask or {}
+        self.nodes = None if nodes is None else np.ascontiguousarray(nodes, dtype=np.float64)
+        self.pre = list(pre or [0.0] * 5) + [0.0] * (5 - len(pre or []))
+        self.post = list(post or [0.0] * 5) + [0.0] * (5 - len(post or []))
+        self.normal = list(normal) + [0.0] * (3 - len(normal))
+        self.offset, self.speed = float(offset), float(speed)
+        self._keep = []
+
+    def c(self):
+        b = _Bcs()
+        self._keep = []
+        for a in range(3):
+            for sd in range(2):
+                b.kind[a][sd] = int(self.kind[a][sd])
+                m = self.mask.get((a, sd))
+                if m is not None:
+                    m = np.ascontiguousarray(m, dtype=np.uint8)
+                    self._keep.append(m)
+                    b.mask[a][sd] = m.ctypes.data
+        if self.nodes is not None:
+            b.nodes = self.nodes.ctypes.data
+        for v in range(5):
+            b.pre[v], b.post[v] = self.pre[v], self.post[v]
+        for c in range(3):
+            b.normal[c] = self.normal[c]
+        b.offset, b.speed = self.offset, self.speed
+        return b
 
 
 def _arr(a):
@@ -217,6 +272,31 @@ def solve(grid: Grid, scheme: Scheme, met, q, dt: float, nsteps: int) -> np.ndar
     _chk(lib().fpo_solve(C.byref(grid.c()), C.byref(scheme.c()), _dp(met), _dp(q), dt,
                          int(nsteps)), "solve")
     return q
+
+
+def apply_bcs(grid: Grid, bcs: Bcs, met, q, t: float) -> np.ndarray:
+    met = _arr(met)
+    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    cb = bcs.c()
+    _chk(lib().fpo_apply_bcs(C.byref(grid.c()), C.byref(cb), _dp(met), _dp(q), float(t)), "apply_bcs")
+    return q
+
+
+def solve_bcs(grid: Grid, scheme: Scheme, bcs: Bcs, met, q, t0: float, dt: float, nsteps: int) -> np.ndarray:
+    met = _arr(met)
+    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    cb = bcs.c()
+    _chk(lib().fpo_solve_bcs(C.byref(grid.c()), C.byref(scheme.c()), C.byref(cb), _dp(met), _dp(q),
+                             float(t0), float(dt), int(nsteps)), "solve_bcs")
+    return q
+
+
+def glf_speeds(grid: Grid, scheme: Scheme, met, q, d: int) -> np.ndarray:
+    met, q = _arr(met), _arr(q)
+    out = np.zeros(3)
+    _chk(lib().fpo_glf_speeds(C.byref(grid.c()), C.byref(scheme.c()), _dp(met), _dp(q), int(d), _dp(out)),
+         "glf_speeds")
+    return out
 
 
 def max_dt(grid: Grid, scheme: Scheme, met, q, cfl: float) -> float:

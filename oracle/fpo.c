@@ -732,8 +732,36 @@ typedef struct {
     const double *S[3];     /* metric vector of the sweep direction, s_{d,c} */
 } line_t;
 
-/* F'_{i+1/2} for the face between nodes i and i+1 of a line */
-static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, double *Fp)
+/* local Lax-Friedrichs speed of every field at the face i+1/2 with unit
+ * normal n and metric norm sigma: the largest sigma |n . u_m + kappa_s c_m|
+ * over the stencil m = i-lo .. i+lo+1 */
+static void llf_speeds(const fpo_scheme *sc, const line_t *ln, int i, const double *n, double sigma,
+                       double *lam)
+{
+    const int ndim = ln->ndim, nv = ln->nv, lo = stencil_lo(sc), ns = 2 * lo + 2;
+    for (int s = 0; s < nv; s++) {
+        double kap = s == 0 ? -1.0 : (s == nv - 1 ? 1.0 : 0.0);
+        lam[s] = 0.0;
+        for (int r = 0; r < ns; r++) {
+            int m = i - lo + r;
+            double Qm[NVMAX];
+            for (int v = 0; v < nv; v++)
+                Qm[v] = ln->Q[v][m];
+            double unm = 0.0;
+            for (int c = 0; c < ndim; c++)
+                unm += n[c] * Qm[1 + c] / Qm[0];
+            double cm = sqrt(sc->gamma * pressure(ndim, sc->gamma, Qm) / Qm[0]);
+            double a = sigma * fabs(unm + kap * cm);
+            if (a > lam[s])
+                lam[s] = a;
+        }
+    }
+}
+
+/* F'_{i+1/2} for the face between nodes i and i+1 of a line; glf = NULL
+ * for local Lax-Friedrichs speeds, else the block's global speeds of the
+ * three field classes (u_n - c, u_n, u_n + c) */
+static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, const double *glf, double *Fp)
 {
     const int ndim = ln->ndim, nv = ln->nv, Y = sc->Y, h = Y / 2;
     const double gam = sc->gamma;
@@ -802,25 +830,15 @@ static void face_flux(const fpo_scheme *sc, const line_t *ln, int i, double *Fp)
     charsys S;
     roe_system(ndim, gam, QL, QR, sf, Vf, &S);
 
-    /* (5) local Lax-Friedrichs speed of every field: the largest
-     * sigma |n . u_m + kappa_s c_m| over the stencil m = i-lo .. i+lo+1 */
+    /* (5) Lax-Friedrichs speed of every field: local (the largest
+     * sigma |n . u_m + kappa_s c_m| over the stencil) or global (the
+     * largest over every face of the block, computed beforehand) */
     double lam[NVMAX];
-    for (int s = 0; s < nv; s++) {
-        double kap = s == 0 ? -1.0 : (s == nv - 1 ? 1.0 : 0.0);
-        lam[s] = 0.0;
-        for (int r = 0; r < ns; r++) {
-            int m = i - lo + r;
-            double Qm[NVMAX];
-            for (int v = 0; v < nv; v++)
-                Qm[v] = ln->Q[v][m];
-            double unm = 0.0;
-            for (int c = 0; c < ndim; c++)
-                unm += S.n[c] * Qm[1 + c] / Qm[0];
-            double cm = sqrt(gam * pressure(ndim, gam, Qm) / Qm[0]);
-            double a = S.sigma * fabs(unm + kap * cm);
-            if (a > lam[s])
-                lam[s] = a;
-        }
+    if (glf) {
+        for (int s = 0; s < nv; s++)
+            lam[s] = s == 0 ? glf[0] : (s == nv - 1 ? glf[2] : glf[1]);
+    } else {
+        llf_speeds(sc, ln, i, S.n, S.sigma, lam);
     }
 
     /* (6) characteristic projection and Lax-Friedrichs splitting:
@@ -926,8 +944,14 @@ static int check_scheme(const layout *L, const fpo_scheme *sc)
      * fifth-order schemes, 4 for WENO7); the face interpolation Y/2 nodes */
     if (L->g < stencil_lo(sc) + 1 || L->g < sc->Y / 2)
         return -1;
-    if (!(sc->gamma > 1.0) || !(sc->eps > 0.0))
+    if (!(sc->gamma > 1.0) || !(sc->eps > 0.0) || (sc->splitting != 0 && sc->splitting != 1))
         return -1;
+    if (sc->mu < 0.0 || (sc->mu > 0.0 && !(sc->prandtl > 0.0)))
+        return -1;
+    if (sc->mu > 0.0)
+        for (int d = 0; d < L->ndim; d++)
+            if (L->bc[d] != 0 || L->n[d] < 7)
+                return -1; /* the viscous stencils wrap periodically */
     return 0;
 }
 
@@ -936,6 +960,84 @@ static void other_axes(int d, int *a, int *b)
 {
     *a = d == 0 ? 1 : 0;
     *b = d == 2 ? 1 : 2;
+}
+
+/* unit normal and metric norm of the face i+1/2: the face metrics and 1/J
+ * interpolated as in step (1) of the face flux, n = s_f/|s_f| and
+ * sigma = |s_f|/(1/J)_f as in the Roe system of step (4) */
+static void face_normal(const fpo_scheme *sc, const line_t *ln, int i, double n[3], double *sigma)
+{
+    const int Y = sc->Y, h = Y / 2, ndim = ln->ndim;
+    double w[8], sf[3] = {0, 0, 0};
+    for (int m = 0; m < Y; m++)
+        w[m] = ln->V[i - h + 1 + m];
+    double Vf = fpo_face_interp(Y, w);
+    for (int c = 0; c < ndim; c++) {
+        for (int m = 0; m < Y; m++)
+            w[m] = ln->S[c][i - h + 1 + m];
+        sf[c] = fpo_face_interp(Y, w);
+    }
+    double snorm = 0.0;
+    for (int c = 0; c < ndim; c++)
+        snorm += sf[c] * sf[c];
+    snorm = sqrt(snorm);
+    n[0] = n[1] = n[2] = 0.0;
+    for (int c = 0; c < ndim; c++)
+        n[c] = sf[c] / snorm;
+    *sigma = snorm / Vf;
+}
+
+/* global Lax-Friedrichs speeds of direction d: the local speeds of every
+ * face of the block (faces i+1/2, i = -1 .. n-1, of every interior line),
+ * maximised per field class */
+static void glf_filled(const layout *L, const fpo_scheme *sc, const double *met, const double *qf,
+                       int d, double out[3])
+{
+    int a, b;
+    other_axes(d, &a, &b);
+    int len = L->n[d] + 2 * L->g;
+    int na = L->n[a], nb = L->n[b];
+    out[0] = out[1] = out[2] = 0.0;
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * len * (L->nv + 1 + L->ndim));
+        double mx[3] = {0.0, 0.0, 0.0};
+        line_t ln;
+#pragma omp for collapse(2) schedule(static)
+        for (int ib = 0; ib < nb; ib++)
+            for (int ia = 0; ia < na; ia++) {
+                int p[3] = {0, 0, 0};
+                p[a] = ia;
+                p[b] = ib;
+                gather_line(L, qf, met, d, p, buf, &ln);
+                for (int f = 0; f <= L->n[d]; f++) {
+                    double n[3], sigma, lam[NVMAX];
+                    face_normal(sc, &ln, f - 1, n, &sigma);
+                    llf_speeds(sc, &ln, f - 1, n, sigma, lam);
+                    mx[0] = fmax(mx[0], lam[0]);
+                    mx[1] = fmax(mx[1], lam[1]);
+                    mx[2] = fmax(mx[2], lam[L->nv - 1]);
+                }
+            }
+#pragma omp critical
+        for (int k = 0; k < 3; k++)
+            out[k] = fmax(out[k], mx[k]);
+        free(buf);
+    }
+}
+
+int fpo_glf_speeds(const fpo_grid *gr, const fpo_scheme *sc, const double *met, const double *q,
+                   int d, double out[3])
+{
+    layout L;
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || d < 0 || d >= L.ndim)
+        return -1;
+    double *qf = filled_copy(&L, q);
+    if (!qf)
+        return -1;
+    glf_filled(&L, sc, met, qf, d, out);
+    free(qf);
+    return 0;
 }
 
 int fpo_face_fluxes(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
@@ -955,6 +1057,11 @@ int fpo_face_fluxes(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
     long fvol = (long)ext[0] * ext[1] * ext[2];
     int na = L.n[a], nb = L.n[b];
     int len = L.n[dir] + 2 * L.g;
+    double glf[3], *gp = NULL;
+    if (sc->splitting) {
+        glf_filled(&L, sc, met, qf, dir, glf);
+        gp = glf;
+    }
 #pragma omp parallel
     {
         double *buf = (double *)malloc(sizeof(double) * len * (L.nv + 1 + L.ndim));
@@ -968,7 +1075,7 @@ int fpo_face_fluxes(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
                 gather_line(&L, qf, met, dir, p, buf, &ln);
                 for (int f = 0; f < nf; f++) {
                     double F[NVMAX];
-                    face_flux(sc, &ln, f - 1, F);
+                    face_flux(sc, &ln, f - 1, gp, F);
                     int c3[3] = {p[0], p[1], p[2]};
                     c3[dir] = f;
                     long off = ((long)c3[2] * ext[1] + c3[1]) * ext[0] + c3[0];
@@ -979,6 +1086,126 @@ int fpo_face_fluxes(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
         free(buf);
     }
     free(qf);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* viscous fluxes (Sec. 2.1 eqs. NSv1-NSv3, stress, strain, heat flux;      */
+/* sixth-order central differences as Sec. 2.2 states), periodic axes       */
+/* ------------------------------------------------------------------------ */
+
+/* sixth-order central first derivative, offsets -3 .. 3 */
+static const double D6[7] = {-1.0 / 60.0, 9.0 / 60.0, -45.0 / 60.0, 0.0, 45.0 / 60.0, -9.0 / 60.0, 1.0 / 60.0};
+
+/* interior node p shifted by `off` along axis d, wrapped periodically */
+static long wrap_at(const layout *L, const int p[3], int d, int off)
+{
+    int c[3] = {p[0], p[1], p[2]};
+    c[d] = ((c[d] + off) % L->n[d] + L->n[d]) % L->n[d];
+    return at(L, c[0], c[1], c[2]);
+}
+
+/* acc -= sum_d D6_d(Fv~_d) at every interior node, where
+ * Fv~_d = sum_j s_{d,j} Fv_j (eq. FGH_v) and, with T = p/rho,
+ * tau_ij = mu (du_i/dx_j + du_j/dx_i - 2/3 delta_ij div u),
+ * Fv_j = (0, tau_1j, .., tau_nj, u_i tau_ij + k dT/dx_j), k = mu gamma/((gamma-1) Pr),
+ * and the gradients at a node by the chain rule
+ * dphi/dx_j = (1/V) sum_d s_{d,j} D6_d(phi). */
+static int viscous_acc(const layout *L, const fpo_scheme *sc, const double *met, const double *q,
+                       double *acc)
+{
+    const int nd = L->ndim, nv = L->nv, np = nd + 1; /* primitives u_1..u_nd, T */
+    const long vol = L->vol;
+    const double gam = sc->gamma, mu = sc->mu;
+    const double kappa = mu * gam / ((gam - 1.0) * sc->prandtl);
+    double *prim = (double *)calloc((size_t)np * vol, sizeof(double));
+    double *fv = (double *)calloc((size_t)nd * nv * vol, sizeof(double));
+    if (!prim || !fv) {
+        free(prim);
+        free(fv);
+        return -1;
+    }
+    for (int k = 0; k < L->n[2]; k++)
+        for (int j = 0; j < L->n[1]; j++)
+            for (int i = 0; i < L->n[0]; i++) {
+                long o = at(L, i, j, k);
+                double Q[NVMAX];
+                for (int v = 0; v < nv; v++)
+                    Q[v] = q[v * vol + o];
+                for (int c = 0; c < nd; c++)
+                    prim[c * vol + o] = Q[1 + c] / Q[0];
+                prim[nd * vol + o] = pressure(nd, gam, Q) / Q[0];
+            }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < L->n[2]; k++)
+        for (int j = 0; j < L->n[1]; j++)
+            for (int i = 0; i < L->n[0]; i++) {
+                int p[3] = {i, j, k};
+                long o = at(L, i, j, k);
+                double V = met[(L->nmet - 1) * vol + o];
+                /* grad[a][jj] = d prim_a / d x_jj */
+                double grad[4][3];
+                for (int a = 0; a < np; a++)
+                    for (int jj = 0; jj < nd; jj++)
+                        grad[a][jj] = 0.0;
+                for (int d = 0; d < nd; d++) {
+                    double dphi[4] = {0, 0, 0, 0};
+                    for (int r = 0; r < 7; r++) {
+                        if (r == 3)
+                            continue;
+                        long om = wrap_at(L, p, d, r - 3);
+                        for (int a = 0; a < np; a++)
+                            dphi[a] += D6[r] * prim[a * vol + om];
+                    }
+                    for (int jj = 0; jj < nd; jj++) {
+                        double s = met[(d * nd + jj) * vol + o];
+                        for (int a = 0; a < np; a++)
+                            grad[a][jj] += s * dphi[a] / V;
+                    }
+                }
+                double div = 0.0;
+                for (int c = 0; c < nd; c++)
+                    div += grad[c][c];
+                double tau[3][3];
+                for (int a = 0; a < nd; a++)
+                    for (int b = 0; b < nd; b++)
+                        tau[a][b] = mu * (grad[a][b] + grad[b][a] - (a == b ? 2.0 / 3.0 * div : 0.0));
+                /* physical viscous fluxes Fv_jj, then contravariant ones */
+                double F[3][NVMAX];
+                for (int jj = 0; jj < nd; jj++) {
+                    F[jj][0] = 0.0;
+                    double work = 0.0;
+                    for (int a = 0; a < nd; a++) {
+                        F[jj][1 + a] = tau[a][jj];
+                        work += prim[a * vol + o] * tau[a][jj];
+                    }
+                    F[jj][nv - 1] = work + kappa * grad[nd][jj];
+                }
+                for (int d = 0; d < nd; d++)
+                    for (int v = 0; v < nv; v++) {
+                        double sum = 0.0;
+                        for (int jj = 0; jj < nd; jj++)
+                            sum += met[(d * nd + jj) * vol + o] * F[jj][v];
+                        fv[((long)d * nv + v) * vol + o] = sum;
+                    }
+            }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < L->n[2]; k++)
+        for (int j = 0; j < L->n[1]; j++)
+            for (int i = 0; i < L->n[0]; i++) {
+                int p[3] = {i, j, k};
+                long o = at(L, i, j, k);
+                for (int d = 0; d < nd; d++)
+                    for (int r = 0; r < 7; r++) {
+                        if (r == 3)
+                            continue;
+                        long om = wrap_at(L, p, d, r - 3);
+                        for (int v = 0; v < nv; v++)
+                            acc[v * vol + o] -= D6[r] * fv[((long)d * nv + v) * vol + om];
+                    }
+            }
+    free(prim);
+    free(fv);
     return 0;
 }
 
@@ -996,6 +1223,11 @@ static int residual_filled(const layout *L, const fpo_scheme *sc, const double *
         other_axes(d, &a, &b);
         int len = L->n[d] + 2 * L->g;
         int na = L->n[a], nb = L->n[b];
+        double glf[3], *gp = NULL;
+        if (sc->splitting) {
+            glf_filled(L, sc, met, qf, d, glf);
+            gp = glf;
+        }
 #pragma omp parallel
         {
             double *buf = (double *)malloc(sizeof(double) * len * (L->nv + 1 + L->ndim));
@@ -1009,7 +1241,7 @@ static int residual_filled(const layout *L, const fpo_scheme *sc, const double *
                     p[b] = ib;
                     gather_line(L, qf, met, d, p, buf, &ln);
                     for (int f = 0; f <= L->n[d]; f++)
-                        face_flux(sc, &ln, f - 1, F + (long)f * NVMAX);
+                        face_flux(sc, &ln, f - 1, gp, F + (long)f * NVMAX);
                     for (int i = 0; i < L->n[d]; i++) {
                         int c3[3] = {p[0], p[1], p[2]};
                         c3[d] = i;
@@ -1022,6 +1254,10 @@ static int residual_filled(const layout *L, const fpo_scheme *sc, const double *
             free(F);
             free(buf);
         }
+    }
+    if (sc->mu > 0.0 && viscous_acc(L, sc, met, qf, acc)) {
+        free(acc);
+        return -1;
     }
     memset(dqdt, 0, sizeof(double) * tot);
     for (int k = 0; k < L->n[2]; k++)
@@ -1050,11 +1286,12 @@ int fpo_residual(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
     return rc;
 }
 
+/* (local speeds only: global ones need the whole block) */
 int fpo_residual_at(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
                     const double *q, int npts, const int *ijk, double *out)
 {
     layout L;
-    if (make_layout(gr, &L) || check_scheme(&L, sc) || npts < 0)
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || npts < 0 || sc->splitting || sc->mu > 0.0)
         return -1;
     for (int t = 0; t < npts; t++)
         for (int d = 0; d < L.ndim; d++) {
@@ -1090,8 +1327,8 @@ int fpo_residual_at(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
                     }
                 }
                 double Fm[NVMAX], Fpl[NVMAX];
-                face_flux(sc, &ln, p[d] - 1, Fm);
-                face_flux(sc, &ln, p[d], Fpl);
+                face_flux(sc, &ln, p[d] - 1, NULL, Fm);
+                face_flux(sc, &ln, p[d], NULL, Fpl);
                 for (int v = 0; v < L.nv; v++)
                     acc[v] += Fpl[v] - Fm[v];
             }
@@ -1113,7 +1350,8 @@ int fpo_residual_at_xyz(const fpo_grid *gr, const fpo_scheme *sc, const double *
 {
     layout L;
     cgrid C;
-    if (make_layout(gr, &L) || check_scheme(&L, sc) || make_cgrid(&L, sc->Y, xyz, &C) || npts < 0)
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || sc->splitting || sc->mu > 0.0 ||
+        make_cgrid(&L, sc->Y, xyz, &C) || npts < 0)
         return -1;
     for (int t = 0; t < npts; t++)
         for (int d = 0; d < L.ndim; d++) {
@@ -1160,8 +1398,8 @@ int fpo_residual_at_xyz(const fpo_grid *gr, const fpo_scheme *sc, const double *
             for (int c = 0; c < nsd; c++)
                 ln.S[c] = buf + (L.nv + 1 + c) * len + R - p[d];
             double Fm[NVMAX], Fpl[NVMAX];
-            face_flux(sc, &ln, p[d] - 1, Fm);
-            face_flux(sc, &ln, p[d], Fpl);
+            face_flux(sc, &ln, p[d] - 1, NULL, Fm);
+            face_flux(sc, &ln, p[d], NULL, Fpl);
             for (int v = 0; v < L.nv; v++)
                 acc[v] += Fpl[v] - Fm[v];
         }
@@ -1172,18 +1410,119 @@ int fpo_residual_at_xyz(const fpo_grid *gr, const fpo_scheme *sc, const double *
 }
 
 /* ------------------------------------------------------------------------ */
+/* boundary faces (the wall-bounded cases of Sec. 4)                        */
+/* ------------------------------------------------------------------------ */
+
+static int check_bcs(const layout *L, const fpo_bcs *bcs)
+{
+    for (int a = 0; a < L->ndim; a++)
+        for (int sd = 0; sd < 2; sd++) {
+            int k = bcs->kind[a][sd];
+            if (k < 0 || k > 3)
+                return -1;
+            if (k && L->bc[a] == 0)
+                return -1; /* periodic axes have no boundary faces */
+            if (k == 2 && L->n[a] < L->g + 1)
+                return -1; /* the mirror images must be interior nodes */
+            if (k == 3 && !bcs->nodes)
+                return -1;
+        }
+    return 0;
+}
+
+/* fill the ghost layers of the boundary faces at time t */
+static void apply_bcs_layout(const layout *L, const fpo_bcs *bcs, const double *met, double *q, double t)
+{
+    const int nv = L->nv, ndim = L->ndim;
+    for (int a = 0; a < ndim; a++) {
+        if (L->bc[a] == 0)
+            continue;
+        int e1, e2;
+        other_axes(a, &e1, &e2);
+        int n1 = L->n[e1], n2 = e2 < ndim ? L->n[e2] : 1;
+        for (int sd = 0; sd < 2; sd++) {
+            int kind = bcs->kind[a][sd];
+            if (kind == 0)
+                continue;
+            int bnode = sd ? L->n[a] - 1 : 0; /* the boundary node along axis a */
+            for (int i2 = 0; i2 < n2; i2++)
+                for (int i1 = 0; i1 < n1; i1++) {
+                    if (bcs->mask[a][sd] && !bcs->mask[a][sd][(long)i2 * n1 + i1])
+                        continue;
+                    int p[3] = {0, 0, 0};
+                    p[e1] = i1;
+                    if (e2 < ndim)
+                        p[e2] = i2;
+                    /* wall normal: the metric vector of axis a at the boundary node */
+                    double nw[3] = {0, 0, 0};
+                    if (kind == 2) {
+                        p[a] = bnode;
+                        long ob = at(L, p[0], p[1], p[2]);
+                        double nn = 0.0;
+                        for (int c = 0; c < ndim; c++) {
+                            nw[c] = met[(a * ndim + c) * L->vol + ob];
+                            nn += nw[c] * nw[c];
+                        }
+                        nn = sqrt(nn);
+                        for (int c = 0; c < ndim; c++)
+                            nw[c] /= nn;
+                    }
+                    for (int l = 1; l <= L->g; l++) {
+                        p[a] = sd ? L->n[a] - 1 + l : -l;
+                        long og = at(L, p[0], p[1], p[2]);
+                        double Q[NVMAX];
+                        if (kind == 1) { /* zeroth-order extrapolation */
+                            p[a] = bnode;
+                            long os = at(L, p[0], p[1], p[2]);
+                            for (int v = 0; v < nv; v++)
+                                Q[v] = q[v * L->vol + os];
+                        } else if (kind == 2) { /* mirror image, normal velocity reversed */
+                            p[a] = sd ? L->n[a] - 1 - l : l;
+                            long os = at(L, p[0], p[1], p[2]);
+                            double un = 0.0;
+                            for (int c = 0; c < ndim; c++)
+                                un += nw[c] * q[(1 + c) * L->vol + os];
+                            Q[0] = q[os];
+                            for (int c = 0; c < ndim; c++)
+                                Q[1 + c] = q[(1 + c) * L->vol + os] - 2.0 * un * nw[c];
+                            Q[nv - 1] = q[(nv - 1) * L->vol + os];
+                        } else { /* moving planar shock */
+                            double xn = 0.0;
+                            for (int c = 0; c < ndim; c++)
+                                xn += bcs->normal[c] * bcs->nodes[c * L->vol + og];
+                            const double *src = xn < bcs->offset + bcs->speed * t ? bcs->post : bcs->pre;
+                            for (int v = 0; v < nv; v++)
+                                Q[v] = src[v];
+                        }
+                        for (int v = 0; v < nv; v++)
+                            q[v * L->vol + og] = Q[v];
+                    }
+                }
+        }
+    }
+}
+
+int fpo_apply_bcs(const fpo_grid *gr, const fpo_bcs *bcs, const double *met, double *q, double t)
+{
+    layout L;
+    if (make_layout(gr, &L) || !bcs || !met || !q || check_bcs(&L, bcs))
+        return -1;
+    apply_bcs_layout(&L, bcs, met, q, t);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* third-order TVD Runge-Kutta (Sec. 2.2)                                   */
 /* ------------------------------------------------------------------------ */
 
 /* Q1 = Qn + dt L(Qn); Q2 = 3/4 Qn + 1/4 (Q1 + dt L(Q1));
- * Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2)); interior nodes only */
-int fpo_rk3_step(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
-                 double *q, double dt)
+ * Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2)); interior nodes only.  With boundary
+ * faces, each stage's input gets its ghost layers at the stage's time
+ * t, t + dt, t + dt/2. */
+static int rk3_step_layout(const layout *L, const fpo_scheme *sc, const fpo_bcs *bcs,
+                           const double *met, double *q, double t, double dt)
 {
-    layout L;
-    if (make_layout(gr, &L) || check_scheme(&L, sc) || !met || !q)
-        return -1;
-    long tot = (long)L.nv * L.vol;
+    long tot = (long)L->nv * L->vol;
     double *q0 = (double *)malloc(sizeof(double) * tot);
     double *qs = (double *)malloc(sizeof(double) * tot);
     double *k = (double *)malloc(sizeof(double) * tot);
@@ -1197,20 +1536,23 @@ int fpo_rk3_step(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
     memcpy(qs, q, sizeof(double) * tot);
     const double a[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
     const double b[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+    const double c[3] = {0.0, 1.0, 0.5};
     int rc = 0;
     for (int st = 0; st < 3 && !rc; st++) {
-        double *qf = filled_copy(&L, qs);
+        if (bcs)
+            apply_bcs_layout(L, bcs, met, qs, t + c[st] * dt);
+        double *qf = filled_copy(L, qs);
         if (!qf) {
             rc = -1;
             break;
         }
-        rc = residual_filled(&L, sc, met, qf, k);
+        rc = residual_filled(L, sc, met, qf, k);
         free(qf);
-        for (int v = 0; v < L.nv; v++)
-            for (int kk = 0; kk < L.n[2]; kk++)
-                for (int j = 0; j < L.n[1]; j++)
-                    for (int i = 0; i < L.n[0]; i++) {
-                        long off = v * L.vol + at(&L, i, j, kk);
+        for (int v = 0; v < L->nv; v++)
+            for (int kk = 0; kk < L->n[2]; kk++)
+                for (int j = 0; j < L->n[1]; j++)
+                    for (int i = 0; i < L->n[0]; i++) {
+                        long off = v * L->vol + at(L, i, j, kk);
                         double upd = qs[off] + dt * k[off];
                         qs[off] = st == 0 ? upd : a[st] * q0[off] + b[st] * upd;
                     }
@@ -1223,11 +1565,34 @@ int fpo_rk3_step(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
     return rc;
 }
 
+int fpo_rk3_step(const fpo_grid *gr, const fpo_scheme *sc, const double *met,
+                 double *q, double dt)
+{
+    layout L;
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || !met || !q)
+        return -1;
+    return rk3_step_layout(&L, sc, NULL, met, q, 0.0, dt);
+}
+
 int fpo_solve(const fpo_grid *gr, const fpo_scheme *sc, const double *met, double *q,
               double dt, long nsteps)
 {
     for (long s = 0; s < nsteps; s++) {
         int rc = fpo_rk3_step(gr, sc, met, q, dt);
+        if (rc)
+            return rc;
+    }
+    return 0;
+}
+
+int fpo_solve_bcs(const fpo_grid *gr, const fpo_scheme *sc, const fpo_bcs *bcs, const double *met,
+                  double *q, double t0, double dt, long nsteps)
+{
+    layout L;
+    if (make_layout(gr, &L) || check_scheme(&L, sc) || !bcs || !met || !q || check_bcs(&L, bcs))
+        return -1;
+    for (long s = 0; s < nsteps; s++) {
+        int rc = rk3_step_layout(&L, sc, bcs, met, q, t0 + s * dt, dt);
         if (rc)
             return rc;
     }

@@ -42,7 +42,38 @@ typedef struct {
     int reformulated;  /* 1: the paper's method; 0: standard scheme (Q* = 0) */
     double gamma;      /* ratio of specific heats */
     double eps;        /* WENO epsilon */
+    int splitting;     /* 0: local Lax-Friedrichs speeds, 1: global (Sec. 4) */
+    double mu;         /* shear viscosity (0: Euler); periodic axes only */
+    double prandtl;    /* Prandtl number: conductivity = mu gamma / ((gamma - 1) Pr), T = p / rho */
 } fpo_scheme;
+
+/* Boundary faces of a block (axis a, side 0 = low, 1 = high), applied to the
+ * ghost layers of every non-periodic axis before each residual evaluation:
+ * 0 hold (ghosts as given), 1 zeroth-order extrapolation (supersonic
+ * outflow), 2 slip wall (mirror image with the normal velocity reversed,
+ * normal from the metrics of the boundary node), 3 moving planar shock
+ * (ghost nodes with normal . x < offset + speed t take `post`, the others
+ * `pre`; conservative states).  mask[a][s], if given, has one byte per node
+ * of the face (first remaining axis fastest): nodes with 0 hold. */
+typedef struct {
+    int kind[3][2];
+    const unsigned char *mask[3][2];
+    const double *nodes; /* coordinates of the state nodes (state layout, ndim arrays) */
+    double pre[5], post[5];
+    double normal[3];
+    double offset, speed;
+} fpo_bcs;
+
+/* the ghost layers of q at time t */
+int fpo_apply_bcs(const fpo_grid *gr, const fpo_bcs *bcs, const double *met, double *q, double t);
+/* TVD RK3 steps from time t0 with the boundary faces applied to each stage's
+ * input at the stage time (t, t + dt, t + dt/2) */
+int fpo_solve_bcs(const fpo_grid *gr, const fpo_scheme *sc, const fpo_bcs *bcs, const double *met,
+                  double *q, double t0, double dt, long nsteps);
+/* the global Lax-Friedrichs speeds of direction d: the largest LLF speed of
+ * every face of the block, per field class (u_n - c, u_n, u_n + c) */
+int fpo_glf_speeds(const fpo_grid *gr, const fpo_scheme *sc, const double *met, const double *q,
+                   int d, double out[3]);
 
 /* Sec. 2.1 eqs. (JBabc),(JB) with the central derivative of eq. (metric_discret). */
 int fpo_metrics(const fpo_grid *gr, int Y, const double *xyz, double *met);

@@ -328,3 +328,140 @@ def interior(a: np.ndarray, g: int) -> np.ndarray:
     """View of the interior nodes of a state-like array (leading variable axis)."""
     nd = a.ndim - 1
     return a[(slice(None),) + (slice(g, -g),) * nd]
+
+
+# ----------------------------------------------------------------------------
+# wall-bounded shock problems (Sec. 4.2): double Mach reflection and the
+# supersonic cylinder.  Grids, initial states and which face is what; the
+# boundary treatment itself belongs to the solver.
+# ----------------------------------------------------------------------------
+
+def _point_reflect(X, idx_ghost, idx_bnd, idx_src):
+    """X[..., ghost] = 2 X[..., boundary] - X[..., source] along the last axes"""
+    X[idx_ghost] = 2.0 * X[idx_bnd] - X[idx_src]
+
+
+def dmr_grid(nx: int = 961, ny: int = 241, rand: float = 0.05, g: int = 3, Y: int = 6, seed: int = 0,
+             Lx: float = 4.0, Ly: float = 1.0) -> np.ndarray:
+    """Grid of the double Mach reflection on [0, Lx] x [0, Ly] with nx x ny
+    nodes, every node moved by ``rand`` of the spacing in a random direction
+    (as the random grid of Sec. 4.1.1); nodes on the boundary lines keep the
+    component along the line only and the corners stay.  Ghost layers: the
+    mirror image of the interior about the bottom wall y = 0, point
+    reflections through the boundary nodes on the other sides."""
+    gc = coord_ghost(g, Y)
+    assert nx > gc and ny > gc
+    hx, hy = Lx / (nx - 1), Ly / (ny - 1)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    x = i * hx
+    y = j * hy
+    ang = rng.uniform(0.0, 2.0 * math.pi, x.shape)
+    dx = rand * hx * np.cos(ang)
+    dy = rand * hy * np.sin(ang)
+    inner_i = (i > 0) & (i < nx - 1)
+    inner_j = (j > 0) & (j < ny - 1)
+    x = x + np.where(inner_i, dx, 0.0)
+    y = y + np.where(inner_j, dy, 0.0)
+    X = np.zeros((2, ny + 2 * gc, nx + 2 * gc))
+    X[:, gc:gc + ny, gc:gc + nx] = np.stack([x, y])
+    rows = slice(gc, gc + ny)
+    for l in range(1, gc + 1):  # left and right: point reflection
+        _point_reflect(X, (slice(None), rows, gc - l), (slice(None), rows, gc), (slice(None), rows, gc + l))
+        r = gc + nx - 1
+        _point_reflect(X, (slice(None), rows, r + l), (slice(None), rows, r), (slice(None), rows, r - l))
+    for l in range(1, gc + 1):  # bottom: mirror about y = 0; top: point reflection
+        X[0, gc - l, :] = X[0, gc + l, :]
+        X[1, gc - l, :] = -X[1, gc + l, :]
+        t = gc + ny - 1
+        _point_reflect(X, (slice(None), t + l, slice(None)), (slice(None), t, slice(None)),
+                       (slice(None), t - l, slice(None)))
+    return np.ascontiguousarray(X)
+
+
+DMR_PRE = (1.4, 0.0, 0.0, 1.0)                  # rho, u, v, p ahead of the shock
+DMR_POST = (8.0, 7.1447, -4.125, 116.5)         # behind it (Mach 10, 60 degrees)
+DMR_X0 = 1.0 / 6.0                               # where the shock meets the wall at t = 0
+DMR_NORMAL = (math.cos(math.pi / 6), -math.sin(math.pi / 6), 0.0)
+DMR_SPEED = 10.0
+
+
+def dmr_state(nodes: np.ndarray, g: int, gamma=GAMMA) -> np.ndarray:
+    """Initial state at the state nodes (ghosts included): post-shock where
+    x - y tan(pi/6) < 1/6, pre-shock elsewhere; the ghost layers below the
+    bottom boundary left of x = 1/6 (its inflow part) hold the post-shock
+    state."""
+    x, y = nodes[0], nodes[1]
+    post = x - y * math.tan(math.pi / 6) < DMR_X0
+    post[:g, :] = nodes[0][:g, :] < DMR_X0
+    rho = np.where(post, DMR_POST[0], DMR_PRE[0])
+    u = np.where(post, DMR_POST[1], DMR_PRE[1])
+    v = np.where(post, DMR_POST[2], DMR_PRE[2])
+    p = np.where(post, DMR_POST[3], DMR_PRE[3])
+    return np.ascontiguousarray(primitive_to_conserved(rho, [u, v], p, gamma))
+
+
+def dmr_faces(nodes: np.ndarray, g: int, gamma=GAMMA) -> dict:
+    """What each face of the double Mach reflection is: left post-shock
+    inflow (held), right outflow (extrapolated), bottom a slip wall from
+    x = 1/6 on (held post-shock inflow before), top the exact moving shock
+    (plane normal . x = cos(pi/6)/6 + 10 t).  mask: one byte per bottom
+    boundary node."""
+    bottom_x = nodes[0][g, g:-g]
+    def cons(s):
+        return [float(a) for a in primitive_to_conserved(np.array(s[0]), [np.array(s[1]), np.array(s[2])],
+                                                          np.array(s[3]), gamma)]
+    return dict(kind=[[0, 1], [2, 3]], mask={(1, 0): (bottom_x >= DMR_X0).astype(np.uint8)},
+                pre=cons(DMR_PRE), post=cons(DMR_POST), normal=DMR_NORMAL,
+                offset=DMR_NORMAL[0] * DMR_X0, speed=DMR_SPEED)
+
+
+def dmr_shock_x(t: float, y: float = 1.0) -> float:
+    """x of the incident shock at height y and time t"""
+    return DMR_X0 + y * math.tan(math.pi / 6) + DMR_SPEED * t / math.cos(math.pi / 6)
+
+
+def cylinder_grid(imax: int = 61, jmax: int = 81, rand: float = 0.2, g: int = 3, Y: int = 6, seed: int = 0,
+                  Rx: float = 3.0, Ry: float = 6.0, theta: float = 5.0 * math.pi / 12.0) -> np.ndarray:
+    """Grid of the supersonic cylinder (Sec. 4.2.2): node (i, j) at
+    x = (Rx - (Rx-1) eta') cos(theta (2 xi' - 1)),
+    y = (Ry - (Ry-1) eta') sin(theta (2 xi' - 1)), xi' = xi/(imax-1),
+    eta' = eta/(jmax-1) with xi = i + rand phi, eta = j + rand sqrt(1 - phi^2),
+    phi ~ U(0, 1) drawn per interior node (boundary nodes unmoved).  Index i
+    runs along the body (axis 0), j from the outer boundary (j = 0) to the
+    cylinder wall r = 1 (j = jmax-1, axis 1).  Ghost layers: the mapping
+    continued, except beyond the wall, where they are the mirror image of the
+    interior about the wall's tangent at each wall node."""
+    gc = coord_ghost(g, Y)
+    assert imax > gc and jmax > gc
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jj, ii = np.meshgrid(np.arange(-gc, jmax + gc, dtype=np.float64), np.arange(-gc, imax + gc, dtype=np.float64),
+                         indexing="ij")
+    phi = rng.uniform(0.0, 1.0, ii.shape)
+    inner = (ii > 0) & (ii < imax - 1) & (jj > 0) & (jj < jmax - 1)
+    xi = ii + np.where(inner, rand * phi, 0.0)
+    eta = jj + np.where(inner, rand * np.sqrt(1.0 - phi * phi), 0.0)
+    xp, ep = xi / (imax - 1), eta / (jmax - 1)
+    X = np.stack([(Rx - (Rx - 1.0) * ep) * np.cos(theta * (2.0 * xp - 1.0)),
+                  (Ry - (Ry - 1.0) * ep) * np.sin(theta * (2.0 * xp - 1.0))])
+    w = gc + jmax - 1  # the wall row
+    for l in range(1, gc + 1):
+        xw = X[:, w, :]
+        nrm = xw / np.linalg.norm(xw, axis=0)
+        d = X[:, w - l, :] - xw
+        X[:, w + l, :] = xw + d - 2.0 * (nrm * d).sum(axis=0) * nrm
+    return np.ascontiguousarray(X)
+
+
+CYL_MACH = 2.0
+
+
+def cylinder_state(ndim_n, g: int, gamma=GAMMA) -> np.ndarray:
+    """Uniform Mach 2 free stream towards -x with p = 1, rho = gamma (c = 1)."""
+    return uniform_state(2, ndim_n, g, gamma, [-CYL_MACH, 0.0], 1.0, gamma)
+
+
+def cylinder_faces() -> dict:
+    """outflow (extrapolated) along the two rays, held free-stream inflow at
+    the outer boundary, slip wall on the cylinder"""
+    return dict(kind=[[1, 1], [0, 2]])
