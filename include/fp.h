@@ -71,6 +71,13 @@ typedef enum {
  * (ghost >= 3; C = 20, q = 2; in FP_MIXED32 its epsilon is floored at 1e-30). */
 enum { FP_WENO5JS = 0, FP_LINUP5 = 1, FP_WENO7JS = 2, FP_WENOCU6 = 3 };
 enum { FP_FP64 = 0, FP_MIXED32 = 1 };            /* precision of the characteristic part */
+/* Lax-Friedrichs speeds of the characteristic splitting (Sec. 3 and 4):
+ * local (the largest sigma |n.u_m + kappa_s c_m| over the face's stencil) or
+ * global (the largest of those over every face of the block in the sweep
+ * direction, per field class u_n - c, u_n, u_n + c; recomputed for every
+ * stage; the paper's choice for the double Mach reflection and the
+ * cylinder). */
+enum { FP_LLF = 0, FP_GLF = 1 };
 enum { FP_BC_PERIODIC = 0, FP_BC_FROZEN = 1 };   /* per axis */
 
 /* One structured block.  ndim = 2 or 3; n[d] >= 1 interior nodes per axis
@@ -98,6 +105,13 @@ typedef struct {
     int32_t precision;
     double gamma;     /* ratio of specific heats, > 1 (the paper: 1.4) */
     double weno_eps;  /* WENO epsilon, > 0 (the paper: 1e-6, for every WENO scheme) */
+    int32_t splitting; /* FP_LLF or FP_GLF; FP_GLF only in fp_rk3_step, fp_solve,
+                          fp_solve_bcs and fp_solve_ns (its speeds live in the workspace) */
+    int32_t reserved;  /* 0 */
+    double mu;         /* shear viscosity; 0 = Euler.  mu > 0 only in fp_viscous_residual and
+                          fp_solve_ns, on grids whose axes are all periodic (n >= 7) */
+    double prandtl;    /* Prandtl number (> 0 when mu > 0); the gas constant is 1 (T = p/rho),
+                          so the conductivity is mu gamma / ((gamma - 1) Pr) */
 } fp_scheme;
 
 /* Sizes in bytes of the caller-allocated arrays. */
@@ -105,7 +119,8 @@ size_t fp_state_bytes(const fp_grid *grid);
 size_t fp_metric_bytes(const fp_grid *grid);
 size_t fp_coord_bytes(const fp_grid *grid, int32_t metric_order);
 /* Workspace of fp_rk3_step / fp_solve: three state-sized arrays (two RK
- * stage registers and the residual accumulator).  When an axis is frozen,
+ * stage registers and the residual accumulator) and 256 bytes for the
+ * global Lax-Friedrichs speeds.  When an axis is frozen,
  * each step first copies the frozen ghost layers of q into the two stage
  * registers. */
 size_t fp_work_bytes(const fp_grid *grid);
@@ -154,6 +169,74 @@ fp_status fp_rk3_step(const fp_grid *grid, const fp_scheme *scheme, const double
  * pointers, dt) captures one step into a HIP graph that later calls replay. */
 fp_status fp_solve(const fp_grid *grid, const fp_scheme *scheme, const double *met,
                    double *q, double *work, double dt, int64_t nsteps, void *stream);
+
+/* Viscous fluxes (Sec. 2.1 eqs. NSv1-NSv3 with the stress, strain and heat
+ * flux definitions), discretised with sixth-order central differences
+ * (Sec. 2.2): at every node the gradients of u and T by the chain rule
+ * dphi/dx_j = J sum_d (xi_d)_{x_j}/J D6_d(phi), the stress
+ * tau_ij = mu (du_i/dx_j + du_j/dx_i - 2/3 delta_ij div u), the physical
+ * fluxes (0, tau_1j, .., u_i tau_ij + kappa dT/dx_j) and their
+ * contravariant combinations Fv~_d = sum_j (xi_d)_{x_j}/J Fv_j; then
+ * dQ/dt gains J sum_d D6_d(Fv~_d) (equal to the difference of sixth-order
+ * face interpolations, so conservative).  Periodic axes only: the ghost
+ * layers cannot hold the gradient stencils' reach.
+ * vwork: fp_viscous_work_bytes(grid) bytes of device memory (the node
+ * fluxes: ndim directions x (ndim + 1) components, state layout). */
+size_t fp_viscous_work_bytes(const fp_grid *grid);
+
+/* dQ/dt of the Navier-Stokes equations: the convective residual of
+ * fp_residual plus the viscous part above (with mu = 0, fp_residual). */
+fp_status fp_viscous_residual(const fp_grid *grid, const fp_scheme *scheme, const double *met,
+                              const double *q, double *dqdt, double *vwork, void *stream);
+
+/* nsteps RK3 steps (Sec. 2.2) of the Navier-Stokes equations; work as for
+ * fp_rk3_step, vwork as above.  Launches eagerly. */
+fp_status fp_solve_ns(const fp_grid *grid, const fp_scheme *scheme, const double *met, double *q,
+                      double *work, double *vwork, double dt, int64_t nsteps, void *stream);
+
+/* Boundary faces of a block for the wall-bounded problems of Sec. 4 (the
+ * double Mach reflection and the supersonic cylinder).  Each face (axis a,
+ * side 0 = low, 1 = high) of a FROZEN axis has a kind, applied to the ghost
+ * layers of the face before every stage:
+ *   FP_FACE_HOLD    ghosts keep the values the caller gave (inflow states);
+ *   FP_FACE_EXTRAP  every ghost layer copies the boundary node (zeroth-order
+ *                   extrapolation: supersonic outflow);
+ *   FP_FACE_WALL    slip wall through the boundary node: ghost layer l takes
+ *                   the state of the interior node l from the boundary with
+ *                   the momentum's component along the wall normal reversed
+ *                   (normal: the boundary node's metric vector of axis a);
+ *                   the coordinates' ghost layers should be the mirror image
+ *                   of the interior nodes, and n[a] > ghost;
+ *   FP_FACE_SHOCK   a planar shock moving along `normal` at `speed`: ghost
+ *                   nodes x with normal . x < offset + speed t take the
+ *                   conservative state `post`, the others `pre`.
+ * mask[a][side], if not NULL, is a device array of one byte per boundary
+ * node of the face (interior nodes of the other axes, the lower-numbered
+ * axis fastest): where it is 0 the face holds.  nodes: device coordinates of
+ * the state nodes (ndim arrays in the state layout), read by FP_FACE_SHOCK
+ * only.  Corner ghost regions are not written (no sweep reads them). */
+enum { FP_FACE_HOLD = 0, FP_FACE_EXTRAP = 1, FP_FACE_WALL = 2, FP_FACE_SHOCK = 3 };
+
+typedef struct {
+    int32_t kind[3][2];
+    const uint8_t *mask[3][2];
+    const double *nodes;
+    double pre[5], post[5];
+    double normal[3];
+    double offset, speed;
+} fp_bcs;
+
+/* The ghost layers of q's boundary faces at time t (one launch per face
+ * whose kind is not FP_FACE_HOLD). */
+fp_status fp_apply_bcs(const fp_grid *grid, const fp_bcs *bcs, const double *met, double *q,
+                       double t, void *stream);
+
+/* nsteps RK3 steps from time t0 with the boundary faces applied to each
+ * stage's input at the stage's time (t, t + dt, t + dt/2; Sec. 2.2).
+ * Launches eagerly (no graph: the stage times change every step). */
+fp_status fp_solve_bcs(const fp_grid *grid, const fp_scheme *scheme, const fp_bcs *bcs,
+                       const double *met, double *q, double *work, double t0, double dt,
+                       int64_t nsteps, void *stream);
 
 /* dt = cfl / max_i sum_d (|s_d . u| + c |s_d|) (1/J)^{-1} over the interior
  * (the convective CFL limit), written to dt_dev (device, one double). */

@@ -121,6 +121,14 @@ fp_status check_scheme(const fp_grid* g, const fp_scheme* s) {
         return fail(FP_EINVAL, "unknown precision %d", s->precision);
     if (!(s->gamma > 1.0)) return fail(FP_EINVAL, "gamma must exceed 1");
     if (!(s->weno_eps > 0.0)) return fail(FP_EINVAL, "weno_eps must be positive");
+    if (s->splitting != FP_LLF && s->splitting != FP_GLF) return fail(FP_EINVAL, "unknown splitting %d", s->splitting);
+    if (!(s->mu >= 0.0)) return fail(FP_EINVAL, "mu must be >= 0");
+    if (s->mu > 0.0) {
+        if (!(s->prandtl > 0.0)) return fail(FP_EINVAL, "prandtl must be positive");
+        for (int d = 0; d < g->ndim; ++d)
+            if (g->bc[d] != FP_BC_PERIODIC || g->n[d] < 7)
+                return fail(FP_EUNSUPPORTED, "viscous fluxes need periodic axes of at least 7 nodes");
+    }
     return FP_OK;
 }
 
@@ -142,11 +150,31 @@ GeoK make_geo(const fp_grid* g) {
     return G;
 }
 
+// The speed floor of local Lax-Friedrichs splitting: zeros in static device
+// memory (zero-initialised, never written), its address fetched once per
+// device with that device current.
+__device__ double g_zero_speeds[16];
+std::mutex g_zero_mu;
+std::map<int, const double*> g_zero_ptr;
+
+const double* zero_speeds() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_zero_mu);
+    auto it = g_zero_ptr.find(dev);
+    if (it != g_zero_ptr.end()) return it->second;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_zero_speeds)) != hipSuccess || !p) return nullptr;
+    g_zero_ptr[dev] = static_cast<const double*>(p);
+    return static_cast<const double*>(p);
+}
+
 SchemeK make_sk(const fp_scheme* s) {
     SchemeK k;
     k.gamma = s->gamma;
     k.eps = s->weno_eps;
     k.reform = s->reformulated;
+    k.glf = nullptr;  // bound by bind_speeds once the arguments are checked
     return k;
 }
 
@@ -205,6 +233,14 @@ fp_status make_ctx(const fp_grid* g, const fp_scheme* s, Ctx& c) {
     return FP_OK;
 }
 
+// the speed floor of the current device (after argument checks: it is the
+// first HIP call of an entry point)
+fp_status bind_speeds(SchemeK& k) {
+    k.glf = zero_speeds();
+    if (!k.glf) return fail(FP_EHIP, "device symbol of the speed floor not found");
+    return FP_OK;
+}
+
 EpiK epi(int mode, double* R) {
     EpiK e;
     std::memset(&e, 0, sizeof e);
@@ -213,27 +249,72 @@ EpiK epi(int mode, double* R) {
     return e;
 }
 
-// one residual evaluation; the last sweep applies `last`
+// the viscous part of the residual accumulator: R = sum_d D6_d(Fv~_d) from
+// the node fluxes of `qs` (written to vwork); the sweeps then accumulate
+void launch_viscous(const Ctx& c, const double* met, const double* qs, double* vwork, double* R,
+                    hipStream_t s) {
+    const long tot = (long)c.G.n[0] * c.G.n[1] * c.G.n[2];
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    const double gam = c.sch.gamma, mu = c.sch.mu;
+    const double kappa = mu * gam / ((gam - 1.0) * c.sch.prandtl);
+    if (c.grid.ndim == 3) {
+        hipLaunchKernelGGL(k_visc_flux<3>, grid, dim3(256), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
+        hipLaunchKernelGGL(k_visc_div<3>, grid, dim3(256), 0, s, c.G, (const double*)vwork, R);
+    } else {
+        hipLaunchKernelGGL(k_visc_flux<2>, grid, dim3(256), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
+        hipLaunchKernelGGL(k_visc_div<2>, grid, dim3(256), 0, s, c.G, (const double*)vwork, R);
+    }
+}
+
+// one residual evaluation; the last sweep applies `last`; with a viscous
+// scheme the viscous part initialises R first
 hipError_t run_residual(const Ctx& c, const double* met, const double* qs, double* R,
-                        const EpiK& last, hipStream_t s) {
+                        const EpiK& last, hipStream_t s, double* vwork = nullptr) {
+    const bool visc = c.sch.mu > 0.0;
+    if (visc) launch_viscous(c, met, qs, vwork, R, s);
     SweepArgs a;
+    std::memset(&a, 0, sizeof a);
     a.G = c.G;
     a.sk = c.sk;
     a.met = met;
     a.qs = qs;
-    a.ep_first = epi(EPI_FIRST, R);
+    a.ep_first = epi(visc ? EPI_MID : EPI_FIRST, R);
     a.ep_mid = epi(EPI_MID, R);
     a.ep_last = last;
     plan_segments(c.G, c.grid.ndim, a);
     return c.stage(a, s);
 }
 
+// the boundary faces of `qs` at time t: one launch per face that is not held
+void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, double t, hipStream_t s) {
+    for (int a = 0; a < c.grid.ndim; ++a)
+        for (int side = 0; side < 2; ++side) {
+            if (bc.kind[a][side] == FP_FACE_HOLD) continue;
+            long total = c.G.g;
+            for (int e = 0; e < 3; ++e)
+                if (e != a) total *= c.G.n[e];
+            const long blocks = (total + 255) / 256;
+            const dim3 grid((unsigned)(blocks < 1024 ? blocks : 1024));
+            if (c.grid.ndim == 3)
+                hipLaunchKernelGGL(k_bc_face<3>, grid, dim3(256), 0, s, c.G, bc, a, side, met, qs, t);
+            else
+                hipLaunchKernelGGL(k_bc_face<2>, grid, dim3(256), 0, s, c.G, bc, a, side, met, qs, t);
+        }
+}
+
 // one TVD RK3 step: q -> A -> B -> q with residual accumulator R; the
-// frozen ghost layers of q are copied into A and B first
-hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, double dt, hipStream_t s) {
+// frozen ghost layers of q are copied into A and B first.  With boundary
+// faces, each stage's input gets its ghost layers at the stage time
+// t, t + dt, t + dt/2; with global LF speeds, the work array's tail holds
+// them.
+hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, double dt, hipStream_t s,
+                   const BcK* bc = nullptr, double t = 0.0, double* vwork = nullptr) {
+    const bool visc = c.sch.mu > 0.0;
     double* A = work;
     double* B = work + c.state_elems;
     double* R = work + 2 * c.state_elems;
+    const double* glf = c.sch.splitting == FP_GLF ? work + 3 * c.state_elems : c.sk.glf;
+    const double stage_t[3] = {t, t + dt, t + 0.5 * dt};
     bool frozen = false;
     for (int d = 0; d < c.grid.ndim; ++d) frozen = frozen || c.grid.bc[d] == FP_BC_FROZEN;
     if (frozen) {
@@ -247,6 +328,8 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
     const double ca[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
     const double cb[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
     for (int k = 0; k < 3; ++k) {
+        if (bc) launch_bcs(c, *bc, met, const_cast<double*>(in[k]), stage_t[k], s);
+        if (visc) launch_viscous(c, met, in[k], vwork, R, s);
         EpiK e = epi(EPI_LAST_RK, R);
         e.stage0 = k == 0;
         e.out = out[k];
@@ -257,11 +340,14 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
         e.a = ca[k];
         e.b = cb[k];
         SweepArgs a;
+        std::memset(&a, 0, sizeof a);
         a.G = c.G;
         a.sk = c.sk;
+        a.sk.glf = glf;
+        a.glf = c.sch.splitting == FP_GLF;
         a.met = met;
         a.qs = in[k];
-        a.ep_first = epi(EPI_FIRST, R);
+        a.ep_first = epi(visc ? EPI_MID : EPI_FIRST, R);
         a.ep_mid = epi(EPI_MID, R);
         a.ep_last = e;
         plan_segments(c.G, c.grid.ndim, a);
@@ -294,6 +380,9 @@ constexpr int kSegTargets[] = {15, 23, 31, 47, 63, 95, 127};
 constexpr int kSegDefault = 31;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// the workspace tail of the global LF speeds (3 directions x 4 slots)
+constexpr size_t kGlfBytes = 256;
 
 }  // namespace
 
@@ -482,7 +571,7 @@ size_t fp_coord_bytes(const fp_grid* g, int32_t Y) {
 
 size_t fp_work_bytes(const fp_grid* g) {
     if (check_grid(g)) return 0;
-    return 3 * fp_state_bytes(g);
+    return 3 * fp_state_bytes(g) + kGlfBytes;
 }
 
 const char* fp_last_error(void) { return g_err.c_str(); }
@@ -550,8 +639,13 @@ fp_status fp_face_fluxes(const fp_grid* g, const fp_scheme* sch, const double* m
     Ctx c;
     fp_status st = make_ctx(g, sch, c);
     if (st) return st;
+    if (sch->mu > 0.0) return fail(FP_EUNSUPPORTED, "viscous schemes take fp_viscous_residual / fp_solve_ns");
+    if (sch->splitting == FP_GLF)
+        return fail(FP_EUNSUPPORTED, "global LF speeds need the workspace of fp_rk3_step / fp_solve");
     if (dir < 0 || dir >= g->ndim) return fail(FP_EINVAL, "dir must be in [0, ndim)");
     if (!met || !q || !flux) return fail(FP_EINVAL, "NULL array");
+    st = bind_speeds(c.sk);
+    if (st) return st;
     faceflux_fn f = get_faceflux_fn(g->ndim, dir, sch->recon, sch->metric_order, sch->precision);
     if (!f) return fail(FP_EUNSUPPORTED, "no face-flux kernel for this scheme");
     hipError_t e = f(c.G, c.sk, met, q, flux, (hipStream_t)stream);
@@ -564,8 +658,13 @@ fp_status fp_residual(const fp_grid* g, const fp_scheme* sch, const double* met,
     Ctx c;
     fp_status st = make_ctx(g, sch, c);
     if (st) return st;
+    if (sch->mu > 0.0) return fail(FP_EUNSUPPORTED, "viscous schemes take fp_viscous_residual / fp_solve_ns");
+    if (sch->splitting == FP_GLF)
+        return fail(FP_EUNSUPPORTED, "global LF speeds need the workspace of fp_rk3_step / fp_solve");
     if (!met || !q || !dqdt) return fail(FP_EINVAL, "NULL array");
     if ((const double*)dqdt == q) return fail(FP_EINVAL, "dqdt must not alias q");
+    st = bind_speeds(c.sk);
+    if (st) return st;
     EpiK last = epi(EPI_LAST_RES, dqdt);
     last.out = dqdt;
     last.metV = met + (size_t)(g->ndim == 3 ? 9 : 4) * c.G.vol;
@@ -579,13 +678,19 @@ fp_status fp_residual_dir(const fp_grid* g, const fp_scheme* sch, const double* 
     Ctx c;
     fp_status st = make_ctx(g, sch, c);
     if (st) return st;
+    if (sch->mu > 0.0) return fail(FP_EUNSUPPORTED, "viscous schemes take fp_viscous_residual / fp_solve_ns");
+    if (sch->splitting == FP_GLF)
+        return fail(FP_EUNSUPPORTED, "global LF speeds need the workspace of fp_rk3_step / fp_solve");
     if (dir < 0 || dir >= g->ndim) return fail(FP_EINVAL, "dir must be in [0, ndim)");
     if (accumulate != 0 && accumulate != 1) return fail(FP_EINVAL, "accumulate must be 0 or 1");
     if (!met || !q || !acc) return fail(FP_EINVAL, "NULL array");
     if ((const double*)acc == q) return fail(FP_EINVAL, "acc must not alias q");
+    st = bind_speeds(c.sk);
+    if (st) return st;
     dir_fn f = get_dir_fn(g->ndim, sch->recon, sch->metric_order, sch->precision);
     if (!f) return fail(FP_EUNSUPPORTED, "no sweep kernel for this scheme");
     SweepArgs a;
+    std::memset(&a, 0, sizeof a);
     a.G = c.G;
     a.sk = c.sk;
     a.met = met;
@@ -601,8 +706,11 @@ fp_status fp_rk3_step(const fp_grid* g, const fp_scheme* sch, const double* met,
     Ctx c;
     fp_status st = make_ctx(g, sch, c);
     if (st) return st;
+    if (sch->mu > 0.0) return fail(FP_EUNSUPPORTED, "viscous schemes take fp_viscous_residual / fp_solve_ns");
     if (!met || !q || !work) return fail(FP_EINVAL, "NULL array");
     if (!(dt > 0.0)) return fail(FP_EINVAL, "dt must be positive");
+    st = bind_speeds(c.sk);
+    if (st) return st;
     hipError_t e = run_rk3(c, met, q, work, dt, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fp_rk3_step launch");
     return FP_OK;
@@ -613,10 +721,13 @@ fp_status fp_solve(const fp_grid* g, const fp_scheme* sch, const double* met, do
     Ctx c;
     fp_status st = make_ctx(g, sch, c);
     if (st) return st;
+    if (sch->mu > 0.0) return fail(FP_EUNSUPPORTED, "viscous schemes take fp_viscous_residual / fp_solve_ns");
     if (!met || !q || !work) return fail(FP_EINVAL, "NULL array");
     if (!(dt > 0.0)) return fail(FP_EINVAL, "dt must be positive");
     if (nsteps < 0) return fail(FP_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return FP_OK;
+    st = bind_speeds(c.sk);
+    if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -669,6 +780,117 @@ fp_status fp_solve(const fp_grid* g, const fp_scheme* sch, const double* met, do
     for (int64_t i = 0; i < nsteps; ++i) {
         e = hipGraphLaunch(exec, s);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    return FP_OK;
+}
+
+fp_status make_bck(const fp_grid* g, const fp_bcs* bcs, BcK& k) {
+    if (!bcs) return fail(FP_EINVAL, "bcs is NULL");
+    std::memset(&k, 0, sizeof k);
+    for (int a = 0; a < 3; ++a)
+        for (int side = 0; side < 2; ++side) {
+            const int kind = bcs->kind[a][side];
+            if (kind < FP_FACE_HOLD || kind > FP_FACE_SHOCK)
+                return fail(FP_EINVAL, "face (%d, %d): unknown kind %d", a, side, kind);
+            if (kind == FP_FACE_HOLD) continue;
+            if (a >= g->ndim) return fail(FP_EINVAL, "face (%d, %d): no such axis", a, side);
+            if (g->bc[a] != FP_BC_FROZEN)
+                return fail(FP_EINVAL, "face (%d, %d): boundary faces need an FP_BC_FROZEN axis", a, side);
+            if (kind == FP_FACE_WALL && g->n[a] < g->ghost + 1)
+                return fail(FP_EINVAL, "face (%d, %d): a wall needs n > ghost along its axis", a, side);
+            if (kind == FP_FACE_SHOCK && !bcs->nodes)
+                return fail(FP_EINVAL, "face (%d, %d): the shock needs the node coordinates", a, side);
+            k.kind[a][side] = kind;
+            k.mask[a][side] = bcs->mask[a][side];
+        }
+    k.nodes = bcs->nodes;
+    for (int v = 0; v < 5; ++v) {
+        k.pre[v] = bcs->pre[v];
+        k.post[v] = bcs->post[v];
+    }
+    for (int c = 0; c < 3; ++c) k.normal[c] = bcs->normal[c];
+    k.offset = bcs->offset;
+    k.speed = bcs->speed;
+    return FP_OK;
+}
+
+fp_status fp_apply_bcs(const fp_grid* g, const fp_bcs* bcs, const double* met, double* q, double t,
+                       void* stream) {
+    fp_status st = check_grid(g);
+    if (st) return st;
+    if (!met || !q) return fail(FP_EINVAL, "NULL array");
+    BcK k;
+    st = make_bck(g, bcs, k);
+    if (st) return st;
+    Ctx c;
+    c.grid = *g;
+    c.G = make_geo(g);
+    launch_bcs(c, k, met, q, t, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "fp_apply_bcs launch");
+    return FP_OK;
+}
+
+fp_status fp_solve_bcs(const fp_grid* g, const fp_scheme* sch, const fp_bcs* bcs, const double* met,
+                       double* q, double* work, double t0, double dt, int64_t nsteps, void* stream) {
+    Ctx c;
+    fp_status st = make_ctx(g, sch, c);
+    if (st) return st;
+    if (sch->mu > 0.0) return fail(FP_EUNSUPPORTED, "viscous schemes take fp_viscous_residual / fp_solve_ns");
+    if (!met || !q || !work) return fail(FP_EINVAL, "NULL array");
+    if (!(dt > 0.0)) return fail(FP_EINVAL, "dt must be positive");
+    if (nsteps < 0) return fail(FP_EINVAL, "nsteps must be >= 0");
+    BcK k;
+    st = make_bck(g, bcs, k);
+    if (st) return st;
+    st = bind_speeds(c.sk);
+    if (st) return st;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        hipError_t e = run_rk3(c, met, q, work, dt, (hipStream_t)stream, &k, t0 + (double)i * dt);
+        if (e != hipSuccess) return hip_fail(e, "fp_solve_bcs launch");
+    }
+    return FP_OK;
+}
+
+size_t fp_viscous_work_bytes(const fp_grid* g) {
+    if (check_grid(g)) return 0;
+    return (size_t)g->ndim * (g->ndim + 1) * fp_state_bytes(g) / (g->ndim + 2);
+}
+
+fp_status fp_viscous_residual(const fp_grid* g, const fp_scheme* sch, const double* met, const double* q,
+                              double* dqdt, double* vwork, void* stream) {
+    Ctx c;
+    fp_status st = make_ctx(g, sch, c);
+    if (st) return st;
+    if (sch->splitting == FP_GLF)
+        return fail(FP_EUNSUPPORTED, "global LF speeds need the workspace of fp_solve_ns");
+    if (!met || !q || !dqdt || (sch->mu > 0.0 && !vwork)) return fail(FP_EINVAL, "NULL array");
+    if ((const double*)dqdt == q) return fail(FP_EINVAL, "dqdt must not alias q");
+    st = bind_speeds(c.sk);
+    if (st) return st;
+    EpiK last = epi(EPI_LAST_RES, dqdt);
+    last.out = dqdt;
+    last.metV = met + (size_t)(g->ndim == 3 ? 9 : 4) * c.G.vol;
+    hipError_t e = run_residual(c, met, q, dqdt, last, (hipStream_t)stream, vwork);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "fp_viscous_residual launch");
+    return FP_OK;
+}
+
+fp_status fp_solve_ns(const fp_grid* g, const fp_scheme* sch, const double* met, double* q, double* work,
+                      double* vwork, double dt, int64_t nsteps, void* stream) {
+    Ctx c;
+    fp_status st = make_ctx(g, sch, c);
+    if (st) return st;
+    if (!met || !q || !work || (sch->mu > 0.0 && !vwork)) return fail(FP_EINVAL, "NULL array");
+    if (!(dt > 0.0)) return fail(FP_EINVAL, "dt must be positive");
+    if (nsteps < 0) return fail(FP_EINVAL, "nsteps must be >= 0");
+    st = bind_speeds(c.sk);
+    if (st) return st;
+    for (int64_t i = 0; i < nsteps; ++i) {
+        hipError_t e = run_rk3(c, met, q, work, dt, (hipStream_t)stream, nullptr, 0.0, vwork);
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "fp_solve_ns launch");
     }
     return FP_OK;
 }
@@ -726,9 +948,15 @@ fp_status fp_batch_create(const fp_scheme* sch, int32_t max_blocks, fp_batch** o
     g3.ghost = sch ? ((sch->metric_order == 8 || sch->recon == FP_WENO7JS) ? 4 : 3) : 3;
     fp_status st = check_scheme(&g3, sch);
     if (st) return st;
+    if (sch->splitting == FP_GLF) return fail(FP_EUNSUPPORTED, "batches use local LF speeds");
+    if (sch->mu > 0.0) return fail(FP_EUNSUPPORTED, "batches are inviscid");
     fp_batch* b = new fp_batch();
     b->sch = *sch;
     b->sk = make_sk(sch);
+    if (bind_speeds(b->sk) != FP_OK) {
+        delete b;
+        return FP_EHIP;
+    }
     b->cap = max_blocks;
     b->maxl = 6 * max_blocks;
     b->part_bytes = part_size(max_blocks, b->maxl);

@@ -24,6 +24,12 @@ struct SchemeK {
     double gamma;
     double eps;
     int reform;  // 1: reference state subtracted (the paper); 0: standard scheme
+    // floor of the Lax-Friedrichs speeds of the sweep direction (u_n - c,
+    // u_n, u_n + c): the face takes max(local speed, floor).  With global
+    // speeds the floor is the block's largest local speed, so the face takes
+    // the global one (at the face that attains it, the larger of the two
+    // roundings); with local speeds it points at zeros.  Never null.
+    const double* glf;
 };
 
 // ---------------------------------------------------------------------------
@@ -509,12 +515,13 @@ __device__ __forceinline__ void face_flux_weno(const LD& ld, const SchemeK& sk,
 #pragma unroll
         for (int v = 0; v < NV; ++v) b[v][r - 1] = pa[v];
     }
-    // local LF speeds: fields (u_n - c), (u_n) x (DIM - 1 + 1), (u_n + c)
+    // LF speeds: fields (u_n - c), (u_n) x (DIM - 1), (u_n + c)
     T lam[NV];
-    lam[0] = S.sigma * mxm;
+    lam[0] = fmax(S.sigma * mxm, T(sk.glf[0]));
+    const T l1 = fmax(S.sigma * mx0, T(sk.glf[1]));
 #pragma unroll
-    for (int v = 1; v < E; ++v) lam[v] = S.sigma * mx0;
-    lam[E] = S.sigma * mxp;
+    for (int v = 1; v < E; ++v) lam[v] = l1;
+    lam[E] = fmax(S.sigma * mxp, T(sk.glf[2]));
     // WENOCU6's eps may be far below the FP32 normal range (1e-40 in the
     // published scheme): the FP32 path floors it at 1e-30
     const T eps = (CU6 && sizeof(T) == 4) ? fmax(T(sk.eps), T(1e-30)) : T(sk.eps);
@@ -575,10 +582,11 @@ __device__ __forceinline__ void face_flux_weno7(const LD& ld, const SchemeK& sk,
         for (int v = 0; v < NV; ++v) b[v][r] = pa[v];
     }
     T lam[NV];
-    lam[0] = S.sigma * mxm;
+    lam[0] = fmax(S.sigma * mxm, T(sk.glf[0]));
+    const T l1 = fmax(S.sigma * mx0, T(sk.glf[1]));
 #pragma unroll
-    for (int v = 1; v < E; ++v) lam[v] = S.sigma * mx0;
-    lam[E] = S.sigma * mxp;
+    for (int v = 1; v < E; ++v) lam[v] = l1;
+    lam[E] = fmax(S.sigma * mxp, T(sk.glf[2]));
     const T eps = T(sk.eps);
     T h[NV];
 #pragma unroll
@@ -639,10 +647,13 @@ __device__ __forceinline__ void face_flux_lu5(const LD& ld, const SchemeK& sk,
 #pragma unroll
     for (int v = 0; v < NV; ++v) w[v] = T(del[v]);
     project<DIM, T>(S, w, pa);
-    pa[0] *= S.sigma * mxm;
+    const T l0 = fmax(S.sigma * mxm, T(sk.glf[0]));
+    const T l1 = fmax(S.sigma * mx0, T(sk.glf[1]));
+    const T l2 = fmax(S.sigma * mxp, T(sk.glf[2]));
+    pa[0] *= l0;
 #pragma unroll
-    for (int v = 1; v < E; ++v) pa[v] *= S.sigma * mx0;
-    pa[E] *= S.sigma * mxp;
+    for (int v = 1; v < E; ++v) pa[v] *= l1;
+    pa[E] *= l2;
     T o[NV];
     backproject<DIM, T>(S, pa, o);
 #pragma unroll

@@ -23,12 +23,32 @@ inline unsigned blocks_for(long threads, int per_block) {
     return (unsigned)((threads + per_block - 1) / per_block);
 }
 
+// the scheme constants of direction d's sweep (its global LF speeds)
+inline SchemeK dir_sk(const SchemeK& sk, int d) {
+    SchemeK k = sk;
+    k.glf += 4 * d;
+    return k;
+}
+
 template <int DIM, int DIR, int Y>
 void launch_wg(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
     constexpr int OTH = DIR == 1 ? 2 : 1;
     const long lblocks = ((long)a.G.n[0] * a.G.n[OTH] + 63) / 64;
     hipLaunchKernelGGL((k_sweep_wg<DIM, DIR, R, Y, P>), dim3((unsigned)(lblocks * a.nseg[DIR])),
-                       dim3(256), 0, s, a.G, a.sk, a.met, a.qs, ep, a.S[DIR]);
+                       dim3(256), 0, s, a.G, dir_sk(a.sk, DIR), a.met, a.qs, ep, a.S[DIR]);
+}
+
+// global LF speeds of every direction from the stage input (when asked for)
+template <int DIM, int Y>
+void launch_glf(const SweepArgs& a, hipStream_t s) {
+    unsigned long long* out = reinterpret_cast<unsigned long long*>(const_cast<double*>(a.sk.glf));
+    hipLaunchKernelGGL(k_glf_reset<DIM>, dim3(1), dim3(64), 0, s, out);
+    for (int d = 0; d < DIM; ++d) {
+        long faces = (long)a.G.n[0] * a.G.n[1] * a.G.n[2] / a.G.n[d] * (a.G.n[d] + 1);
+        const long blocks = (faces + 255) / 256;
+        hipLaunchKernelGGL((k_glf<DIM, Y, R == 2 ? 3 : 2>), dim3((unsigned)(blocks < 2048 ? blocks : 2048)),
+                           dim3(256), 0, s, a.G, a.sk.gamma, a.met, a.qs, d, out);
+    }
 }
 
 // resident workgroups of a kernel on the current device (queried once)
@@ -55,6 +75,7 @@ void launch_x(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
 
 template <int DIM, int Y>
 hipError_t run_stage(const SweepArgs& a, hipStream_t s) {
+    if (a.glf) launch_glf<DIM, Y>(a, s);
     launch_x<DIM, Y>(a, a.ep_first, s);
     if constexpr (DIM == 3) {
         launch_wg<3, 1, Y>(a, a.ep_mid, s);

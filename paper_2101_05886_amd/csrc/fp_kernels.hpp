@@ -567,6 +567,103 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK 
 }
 
 // ---------------------------------------------------------------------------
+// global Lax-Friedrichs speeds
+// ---------------------------------------------------------------------------
+
+// Zero the speed slots (3 per direction, 4 apart) before the reductions
+// (a template: this header is compiled into several objects).
+template <int DIM>
+__global__ void k_glf_reset(unsigned long long* out) {
+    if (threadIdx.x < 12) out[threadIdx.x] = 0ull;
+}
+
+// The largest local Lax-Friedrichs speed over every face of direction d
+// (faces f + 1/2, f = -1 .. n_d - 1, of every interior line), per field class
+// (u_n - c, u_n, u_n + c): at each face the metric vector and 1/J are
+// interpolated (order Y) as for the face's reference state, n = s_f/|s_f|,
+// sigma = |s_f|/(1/J)_f, and the speeds sigma |n . u_m + kappa c_m| are
+// maximised over the stencil nodes m = f - LO .. f + LO + 1.  As in the
+// sweeps, the state's index wraps into the interior on a periodic axis (its
+// ghost layers are not filled) and the metrics are read in place.  One
+// thread per face; the non-negative doubles are reduced as integers (their
+// bit patterns order as the values do).
+template <int DIM, int Y, int LO>
+__global__ __launch_bounds__(256) void k_glf(GeoK G, double gamma, const double* __restrict__ met,
+                                              const double* __restrict__ q, int d,
+                                              unsigned long long* __restrict__ out) {
+    constexpr int E = DIM + 1, NMET = DIM == 3 ? 10 : 5;
+    const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+    const long n1 = G.n[e1], n2 = G.n[e2], nf = G.n[d] + 1;
+    const long total = nf * n1 * n2;
+    const long sdd = G.sd[d];
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        const int f = (int)(t % nf) - 1;
+        const long r = t / nf;
+        const long line = G.base + (r % n1) * G.sd[e1] + (r / n1) * G.sd[e2];
+        double Vf = 0.0, sf[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) sf[c] = 0.0;
+#pragma unroll
+        for (int m = 0; m < Y; ++m) {
+            const long off = line + (long)(f - Y / 2 + 1 + m) * sdd;
+            const double w = iw<Y>(m + 4 - Y / 2);
+            Vf += w * met[(NMET - 1) * G.vol + off];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) sf[c] += w * met[(d * DIM + c) * G.vol + off];
+        }
+        double s2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) s2 += sf[c] * sf[c];
+        const double sn = sqrt(s2);
+        const double sigma = sn / Vf;
+        double n[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) n[c] = sf[c] / sn;
+        const int nd = G.n[d];
+        const bool per = G.bc[d] == 0;
+#pragma unroll
+        for (int m = -LO; m <= LO + 1; ++m) {
+            int t2 = f + m;
+            if (per) t2 = t2 < 0 ? t2 + nd : (t2 >= nd ? t2 - nd : t2);
+            const long off = line + (long)t2 * sdd;
+            const double rho = q[off];
+            double un = 0.0, k2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const double mc = q[(1 + c) * G.vol + off];
+                un += n[c] * mc / rho;
+                k2 += mc * mc / rho;
+            }
+            const double p = (gamma - 1.0) * (q[E * G.vol + off] - 0.5 * k2);
+            const double cs = sqrt(gamma * p / rho);
+            m0 = fmax(m0, sigma * fabs(un - cs));
+            m1 = fmax(m1, sigma * fabs(un));
+            m2 = fmax(m2, sigma * fabs(un + cs));
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        m0 = fmax(m0, __shfl_xor(m0, o));
+        m1 = fmax(m1, __shfl_xor(m1, o));
+        m2 = fmax(m2, __shfl_xor(m2, o));
+    }
+    __shared__ double red[3][4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = m0;
+        red[1][w] = m1;
+        red[2][w] = m2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        const double v = fmax(fmax(red[k][0], red[k][1]), fmax(red[k][2], red[k][3]));
+        atomicMax(out + 4 * d + k, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // batches: many blocks (of one dimensionality and scheme) in shared launches
 // ---------------------------------------------------------------------------
 
@@ -750,6 +847,7 @@ struct SweepArgs {
     EpiK ep_first, ep_mid, ep_last;
     int S[3];
     int nseg[3];
+    int glf;  // 1: reduce the global LF speeds of the stage input into sk.glf first
 };
 
 // one full residual evaluation (all sweeps) of the given instantiation

@@ -254,6 +254,213 @@ __global__ __launch_bounds__(256) void kb_halo(const int* __restrict__ t_nlink,
 }
 
 // ---------------------------------------------------------------------------
+// boundary faces
+// ---------------------------------------------------------------------------
+
+struct BcK {
+    int kind[3][2];  // 0 hold, 1 extrapolate, 2 slip wall, 3 moving planar shock
+    const unsigned char* mask[3][2];
+    const double* nodes;
+    double pre[5], post[5];
+    double normal[3];
+    double offset, speed;
+};
+
+// The ghost layers l = 1..g of face (a, side) at time t, one thread per
+// (boundary node, layer): extrapolation copies the boundary node; the slip
+// wall takes the mirror node l (from the boundary) with the momentum's
+// component along the boundary node's unit metric vector of axis a
+// reversed; the shock sets post or pre by the side of the moving plane.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_bc_face(GeoK G, BcK bc, int a, int side,
+                                                  const double* __restrict__ met, double* __restrict__ q,
+                                                  double t) {
+    constexpr int NV = DIM + 2, E = NV - 1;
+    const int e1 = a == 0 ? 1 : 0, e2 = a == 2 ? 1 : 2;
+    const long n1 = G.n[e1], n2 = G.n[e2];
+    const int g = G.g, kind = bc.kind[a][side], nb = G.n[a];
+    const unsigned char* mask = bc.mask[a][side];
+    const long total = n1 * n2 * g, sa = G.sd[a];
+    for (long tt = (long)blockIdx.x * blockDim.x + threadIdx.x; tt < total; tt += (long)gridDim.x * blockDim.x) {
+        const long i1 = tt % n1, r = tt / n1;
+        const int l = (int)(r % g) + 1;
+        const long i2 = r / g;
+        if (mask && !mask[i2 * n1 + i1]) continue;
+        const long line = G.base + i1 * G.sd[e1] + i2 * G.sd[e2];
+        const long og = line + (long)(side ? nb - 1 + l : -l) * sa;
+        double Q[NV];
+        if (kind == 1) {
+            const long os = line + (long)(side ? nb - 1 : 0) * sa;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Q[v] = q[v * G.vol + os];
+        } else if (kind == 2) {
+            const long ob = line + (long)(side ? nb - 1 : 0) * sa;
+            double nw[DIM], nn = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                nw[c] = met[(a * DIM + c) * G.vol + ob];
+                nn += nw[c] * nw[c];
+            }
+            nn = sqrt(nn);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) nw[c] /= nn;
+            const long os = line + (long)(side ? nb - 1 - l : l) * sa;
+            double un = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) un += nw[c] * q[(1 + c) * G.vol + os];
+            Q[0] = q[os];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) Q[1 + c] = q[(1 + c) * G.vol + os] - 2.0 * un * nw[c];
+            Q[E] = q[E * G.vol + os];
+        } else {
+            double xn = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) xn += bc.normal[c] * bc.nodes[c * G.vol + og];
+            const bool behind = xn < bc.offset + bc.speed * t;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Q[v] = behind ? bc.post[v] : bc.pre[v];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) q[v * G.vol + og] = Q[v];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// viscous fluxes (periodic axes): node fluxes, then their central difference
+// ---------------------------------------------------------------------------
+
+// sixth-order central first derivative, offsets 1..3 (antisymmetric)
+__device__ __forceinline__ double d6w(int o) { return o == 1 ? 45.0 / 60.0 : (o == 2 ? -9.0 / 60.0 : 1.0 / 60.0); }
+
+// interior node `off` shifted by s along axis d with the periodic wrap
+__device__ __forceinline__ long wrap_node(const GeoK& G, long off, int idx, int d, int s) {
+    int t = idx + s;
+    t = t < 0 ? t + G.n[d] : (t >= G.n[d] ? t - G.n[d] : t);
+    return off + (long)(t - idx) * G.sd[d];
+}
+
+// primitives (u_1 .. u_DIM, T = p / rho) of node o
+template <int DIM>
+__device__ __forceinline__ void visc_prim(const double* __restrict__ q, long vol, long o, double gm1,
+                                          double (&w)[DIM + 1]) {
+    const double rho = q[o];
+    const double ir = 1.0 / rho;
+    double k2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double m = q[(1 + c) * vol + o];
+        w[c] = m * ir;
+        k2 += m * w[c];
+    }
+    w[DIM] = gm1 * (q[(DIM + 1) * vol + o] - 0.5 * k2) * ir;
+}
+
+// Contravariant viscous fluxes of every direction at every interior node:
+// gradients by the chain rule dphi/dx_j = (1/V) sum_d s_{d,j} D6_d(phi),
+// tau_ij = mu (du_i/dx_j + du_j/dx_i - 2/3 delta_ij div u), the physical
+// fluxes (tau_1j .. tau_nj, u_i tau_ij + kappa dT/dx_j) and
+// Fv~_d = sum_j s_{d,j} Fv_j.  fv: [DIM directions][DIM + 1 components]
+// arrays in the state layout (the mass component, zero, is not stored).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_visc_flux(GeoK G, double gamma, double mu, double kappa,
+                                                    const double* __restrict__ met,
+                                                    const double* __restrict__ q, double* __restrict__ fv) {
+    constexpr int NP = DIM + 1, NMET = DIM == 3 ? 10 : 5;
+    const long tot = (long)G.n[0] * G.n[1] * G.n[2];
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tot) return;
+    int idx[3];
+    idx[0] = (int)(t % G.n[0]);
+    idx[1] = (int)((t / G.n[0]) % G.n[1]);
+    idx[2] = (int)(t / ((long)G.n[0] * G.n[1]));
+    const long o = G.base + idx[0] + idx[1] * G.sd[1] + (long)idx[2] * G.sd[2];
+    const double gm1 = gamma - 1.0;
+    const double iV = 1.0 / met[(NMET - 1) * G.vol + o];
+    double grad[NP][DIM];
+#pragma unroll
+    for (int a = 0; a < NP; ++a)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) grad[a][j] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        double dphi[NP];
+#pragma unroll
+        for (int a = 0; a < NP; ++a) dphi[a] = 0.0;
+#pragma unroll
+        for (int s = 1; s <= 3; ++s) {
+            double wp[NP], wm[NP];
+            visc_prim<DIM>(q, G.vol, wrap_node(G, o, idx[d], d, s), gm1, wp);
+            visc_prim<DIM>(q, G.vol, wrap_node(G, o, idx[d], d, -s), gm1, wm);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) dphi[a] += d6w(s) * (wp[a] - wm[a]);
+        }
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+            const double sdj = met[(d * DIM + j) * G.vol + o] * iV;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) grad[a][j] += sdj * dphi[a];
+        }
+    }
+    double w[NP];
+    visc_prim<DIM>(q, G.vol, o, gm1, w);
+    double div = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) div += grad[c][c];
+    double F[DIM][NP];  // physical fluxes Fv_j, components 1..DIM+1
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+        double work = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const double tau = mu * (grad[a][j] + grad[j][a] - (a == j ? 2.0 / 3.0 * div : 0.0));
+            F[j][a] = tau;
+            work += w[a] * tau;
+        }
+        F[j][DIM] = work + kappa * grad[DIM][j];
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int v = 0; v < NP; ++v) {
+            double sum = 0.0;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) sum += met[(d * DIM + j) * G.vol + o] * F[j][v];
+            fv[(d * NP + v) * G.vol + o] = sum;
+        }
+}
+
+// R = sum_d D6_d(Fv~_d) at every interior node (the mass component 0): the
+// viscous part of the residual accumulator, before the inviscid sweeps
+// subtract their flux differences.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_visc_div(GeoK G, const double* __restrict__ fv, double* __restrict__ R) {
+    constexpr int NP = DIM + 1;
+    const long tot = (long)G.n[0] * G.n[1] * G.n[2];
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tot) return;
+    int idx[3];
+    idx[0] = (int)(t % G.n[0]);
+    idx[1] = (int)((t / G.n[0]) % G.n[1]);
+    idx[2] = (int)(t / ((long)G.n[0] * G.n[1]));
+    const long o = G.base + idx[0] + idx[1] * G.sd[1] + (long)idx[2] * G.sd[2];
+    double acc[NP];
+#pragma unroll
+    for (int v = 0; v < NP; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+#pragma unroll
+        for (int s = 1; s <= 3; ++s) {
+            const long op = wrap_node(G, o, idx[d], d, s), om = wrap_node(G, o, idx[d], d, -s);
+#pragma unroll
+            for (int v = 0; v < NP; ++v)
+                acc[v] += d6w(s) * (fv[(d * NP + v) * G.vol + op] - fv[(d * NP + v) * G.vol + om]);
+        }
+    R[o] = 0.0;
+#pragma unroll
+    for (int v = 0; v < NP; ++v) R[(1 + v) * G.vol + o] = acc[v];
+}
+
+// ---------------------------------------------------------------------------
 // CFL limit and state check
 // ---------------------------------------------------------------------------
 

@@ -19,11 +19,14 @@ FP_OK, FP_EINVAL, FP_EUNSUPPORTED, FP_EHIP, FP_ENOMEM, FP_ENONPHYS = 0, -1, -2, 
 FP_WENO5JS, FP_LINUP5, FP_WENO7JS, FP_WENOCU6 = 0, 1, 2, 3
 FP_FP64, FP_MIXED32 = 0, 1
 FP_BC_PERIODIC, FP_BC_FROZEN = 0, 1
+FP_LLF, FP_GLF = 0, 1
+FP_FACE_HOLD, FP_FACE_EXTRAP, FP_FACE_WALL, FP_FACE_SHOCK = 0, 1, 2, 3
 
 EXPORTS = ["fp_state_bytes", "fp_metric_bytes", "fp_coord_bytes", "fp_work_bytes", "fp_metrics",
            "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve", "fp_max_dt",
            "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step", "fp_batch_solve",
-           "fp_batch_set_links", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error"]
+           "fp_batch_set_links", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error",
+           "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_work_bytes", "fp_viscous_residual", "fp_solve_ns"]
 
 
 class FPError(RuntimeError):
@@ -39,7 +42,15 @@ class FPGrid(C.Structure):
 
 class FPScheme(C.Structure):
     _fields_ = [("recon", C.c_int32), ("metric_order", C.c_int32), ("reformulated", C.c_int32),
-                ("precision", C.c_int32), ("gamma", C.c_double), ("weno_eps", C.c_double)]
+                ("precision", C.c_int32), ("gamma", C.c_double), ("weno_eps", C.c_double),
+                ("splitting", C.c_int32), ("reserved", C.c_int32), ("mu", C.c_double),
+                ("prandtl", C.c_double)]
+
+
+class FPBcs(C.Structure):
+    _fields_ = [("kind", (C.c_int32 * 2) * 3), ("mask", (C.c_void_p * 2) * 3), ("nodes", C.c_void_p),
+                ("pre", C.c_double * 5), ("post", C.c_double * 5), ("normal", C.c_double * 3),
+                ("offset", C.c_double), ("speed", C.c_double)]
 
 
 class FPBlock(C.Structure):
@@ -62,7 +73,7 @@ def lib():
             raise FPError(FP_EHIP, f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
         gp, sp, vp, dp = C.POINTER(FPGrid), C.POINTER(FPScheme), C.c_void_p, C.c_void_p
-        for name in ("fp_state_bytes", "fp_metric_bytes", "fp_work_bytes"):
+        for name in ("fp_state_bytes", "fp_metric_bytes", "fp_work_bytes", "fp_viscous_work_bytes"):
             getattr(L, name).argtypes = [gp]
             getattr(L, name).restype = C.c_size_t
         L.fp_coord_bytes.argtypes = [gp, C.c_int32]
@@ -74,6 +85,10 @@ def lib():
         L.fp_rk3_step.argtypes = [gp, sp, dp, dp, dp, C.c_double, vp]
         L.fp_solve.argtypes = [gp, sp, dp, dp, dp, C.c_double, C.c_int64, vp]
         L.fp_max_dt.argtypes = [gp, sp, dp, dp, C.c_double, dp, vp]
+        L.fp_apply_bcs.argtypes = [gp, C.POINTER(FPBcs), dp, dp, C.c_double, vp]
+        L.fp_viscous_residual.argtypes = [gp, sp, dp, dp, dp, dp, vp]
+        L.fp_solve_ns.argtypes = [gp, sp, dp, dp, dp, dp, C.c_double, C.c_int64, vp]
+        L.fp_solve_bcs.argtypes = [gp, sp, C.POINTER(FPBcs), dp, dp, dp, C.c_double, C.c_double, C.c_int64, vp]
         L.fp_check_state.argtypes = [gp, sp, dp, dp, vp]
         bp = C.c_void_p
         L.fp_batch_create.argtypes = [sp, C.c_int32, C.POINTER(C.c_void_p)]
@@ -91,7 +106,8 @@ def lib():
         L.fp_last_error.restype = C.c_char_p
         for name in ("fp_metrics", "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve",
                      "fp_max_dt", "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step",
-                     "fp_batch_solve", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_set_links"):
+                     "fp_batch_solve", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_set_links",
+                     "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_residual", "fp_solve_ns"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -144,15 +160,21 @@ class Grid:
         return (self.ndim,) + tuple(reversed(ext))
 
     def work_shape(self):
-        """the RK3 workspace (see fp_work_bytes): three state-sized arrays"""
-        return (3,) + self.state_shape()
+        """the RK3 workspace (see fp_work_bytes), flat: three state-sized
+        arrays and 32 doubles for the global LF speeds"""
+        vol = 1
+        for e in self.state_shape():
+            vol *= e
+        return (3 * vol + 32,)
 
 
 class Scheme:
     def __init__(self, recon="weno5", metric_order=6, reformulated=True, precision="fp64",
-                 gamma=1.4, weno_eps=1e-6):
+                 gamma=1.4, weno_eps=1e-6, splitting="llf", mu=0.0, prandtl=0.72):
         self.recon = {"weno5": FP_WENO5JS, "linup5": FP_LINUP5, "weno7": FP_WENO7JS,
                       "wenocu6": FP_WENOCU6}.get(recon, recon)
+        self.splitting = {"llf": FP_LLF, "glf": FP_GLF}.get(splitting, splitting)
+        self.mu, self.prandtl = float(mu), float(prandtl)
         self.precision = {"fp64": FP_FP64, "mixed": FP_MIXED32}.get(precision, precision)
         self.metric_order, self.reformulated = int(metric_order), int(bool(reformulated))
         self.gamma, self.weno_eps = float(gamma), float(weno_eps)
@@ -161,7 +183,56 @@ class Scheme:
         s = FPScheme()
         s.recon, s.metric_order, s.reformulated = int(self.recon), self.metric_order, self.reformulated
         s.precision, s.gamma, s.weno_eps = int(self.precision), self.gamma, self.weno_eps
+        s.splitting, s.reserved = int(self.splitting), 0
+        s.mu, s.prandtl = self.mu, self.prandtl
         return s
+
+
+class Bcs:
+    """Boundary faces (fp_apply_bcs): kind[axis][side] in FP_FACE_*, optional
+    uint8 GPU masks per face {(axis, side): tensor} (1 = the kind applies),
+    the state nodes' coordinates (float64 GPU tensor, ndim x state layout)
+    for FP_FACE_SHOCK, and the shock's conservative states and plane."""
+
+    def __init__(self, kind, mask=None, nodes=None, pre=None, post=None, normal=(1.0, 0.0, 0.0),
+                 offset=0.0, speed=0.0):
+        self.kind = [list(k) for k in kind] + [[FP_FACE_HOLD, FP_FACE_HOLD]] * (3 - len(kind))
+        self.mask = dict(mask or {})
+        for m in self.mask.values():
+            if not isinstance(m, torch.Tensor) or not m.is_cuda or m.dtype != torch.uint8 or not m.is_contiguous():
+                raise FPError(FP_EINVAL, "masks must be contiguous uint8 tensors on the GPU")
+        if nodes is not None and (not nodes.is_cuda or nodes.dtype != torch.float64 or not nodes.is_contiguous()):
+            raise FPError(FP_EINVAL, "nodes must be a contiguous float64 tensor on the GPU")
+        self.nodes = nodes
+        self.pre = list(pre or []) + [0.0] * (5 - len(pre or []))
+        self.post = list(post or []) + [0.0] * (5 - len(post or []))
+        self.normal = list(normal) + [0.0] * (3 - len(normal))
+        self.offset, self.speed = float(offset), float(speed)
+
+    def c(self, grid: "Grid"):
+        b = FPBcs()
+        for a in range(3):
+            for sd in range(2):
+                b.kind[a][sd] = int(self.kind[a][sd])
+                m = self.mask.get((a, sd))
+                if m is not None:
+                    need = 1
+                    for e in range(grid.ndim):
+                        if e != a:
+                            need *= grid.n[e]
+                    if m.numel() < need:
+                        raise FPError(FP_EINVAL, f"mask of face ({a}, {sd}) needs {need} bytes")
+                    b.mask[a][sd] = m.data_ptr()
+        if self.nodes is not None:
+            if self.nodes.numel() * 8 < grid.ndim * state_bytes(grid) // grid.nv:
+                raise FPError(FP_EINVAL, "nodes is smaller than ndim state-layout arrays")
+            b.nodes = self.nodes.data_ptr()
+        for v in range(5):
+            b.pre[v], b.post[v] = float(self.pre[v]), float(self.post[v])
+        for c in range(3):
+            b.normal[c] = float(self.normal[c])
+        b.offset, b.speed = self.offset, self.speed
+        return b
 
 
 def _dev(t: torch.Tensor, nbytes: int, name: str):
@@ -255,6 +326,50 @@ def solve(grid: Grid, scheme: Scheme, met, q, work, dt: float, nsteps: int) -> t
     _check(lib().fp_solve(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
                           _dev(q, state_bytes(grid), "q"), _dev(work, work_bytes(grid), "work"),
                           float(dt), int(nsteps), _stream()))
+    return q
+
+
+def viscous_work_bytes(grid: Grid) -> int:
+    g = grid.c()
+    return int(lib().fp_viscous_work_bytes(C.byref(g)))
+
+
+def viscous_work(grid: Grid, device="cuda") -> torch.Tensor:
+    """the viscous node-flux workspace (fp_viscous_work_bytes), flat"""
+    return torch.zeros(viscous_work_bytes(grid) // 8, dtype=torch.float64, device=device)
+
+
+def viscous_residual(grid: Grid, scheme: Scheme, met, q, vwork, dqdt=None) -> torch.Tensor:
+    if dqdt is None:
+        dqdt = torch.zeros_like(q)
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_viscous_residual(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                                     _dev(q, state_bytes(grid), "q"), _dev(dqdt, state_bytes(grid), "dqdt"),
+                                     _dev(vwork, viscous_work_bytes(grid), "vwork"), _stream()))
+    return dqdt
+
+
+def solve_ns(grid: Grid, scheme: Scheme, met, q, work, vwork, dt: float, nsteps: int) -> torch.Tensor:
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_solve_ns(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                             _dev(q, state_bytes(grid), "q"), _dev(work, work_bytes(grid), "work"),
+                             _dev(vwork, viscous_work_bytes(grid), "vwork"), float(dt), int(nsteps), _stream()))
+    return q
+
+
+def apply_bcs(grid: Grid, bcs: Bcs, met, q, t: float) -> torch.Tensor:
+    g, b = grid.c(), bcs.c(grid)
+    _check(lib().fp_apply_bcs(C.byref(g), C.byref(b), _dev(met, metric_bytes(grid), "met"),
+                              _dev(q, state_bytes(grid), "q"), float(t), _stream()))
+    return q
+
+
+def solve_bcs(grid: Grid, scheme: Scheme, bcs: Bcs, met, q, work, t0: float, dt: float,
+              nsteps: int) -> torch.Tensor:
+    g, s, b = grid.c(), scheme.c(), bcs.c(grid)
+    _check(lib().fp_solve_bcs(C.byref(g), C.byref(s), C.byref(b), _dev(met, metric_bytes(grid), "met"),
+                              _dev(q, state_bytes(grid), "q"), _dev(work, work_bytes(grid), "work"),
+                              float(t0), float(dt), int(nsteps), _stream()))
     return q
 
 
