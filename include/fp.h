@@ -255,9 +255,10 @@ fp_status fp_check_state(const fp_grid *grid, const fp_scheme *scheme, const dou
  * with one scheme, by the RK3 step of fp_rk3_step (Sec. 2.2), each block
  * with its own dt.  Per RK stage every sweep direction is ONE persistent
  * launch over a (block, tile) work list of all blocks of a dimensionality;
- * a step is 1 + 3 x (1 + ndim) such launches (ghost copy, then per stage the
- * interface exchange and the sweeps), captured once into a HIP graph by
- * fp_batch_solve.  Per block the arithmetic is that of fp_rk3_step, and the
+ * a step is 1 + 3 x ndim such launches (ghost copy, then per stage the
+ * sweeps), plus one interface exchange per stage when blocks of that
+ * dimensionality are linked, captured once per such configuration into a
+ * HIP graph by fp_batch_solve.  Per block the arithmetic is that of fp_rk3_step, and the
  * result is bitwise the same as advancing the block alone.
  *
  * Ownership: the batch owns its device work-list tables and a pinned host

@@ -407,7 +407,9 @@ struct fp_batch {
     const LinkK* lnk[2] = {nullptr, nullptr};     // device: the links
     int grid[2][BK_KINDS]{};
     batch_stage_fn fn[2] = {nullptr, nullptr};
-    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};  // by mask of non-empty parts
+    // step graphs by mask: bits 0/1 non-empty 2D/3D part, bits 2/3 that part has links
+    hipGraphExec_t graph[16] = {};
+    int nlink[2] = {0, 0};  // links per part (no exchange launches without)
     hipStream_t cs = nullptr;
 };
 
@@ -438,7 +440,7 @@ int seg_len(int nd, int target) {
 
 // Host image of the tables of both parts for `blocks` (already validated).
 void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, const std::vector<fp_link>& links,
-                  char* img, int nblk[2]) {
+                  char* img, int nblk[2], int nlink[2]) {
     for (int p = 0; p < 2; ++p) {
         char* base = img + p * b->part_bytes;
         long* start = reinterpret_cast<long*>(base + start_offset());
@@ -498,6 +500,7 @@ void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, const 
         }
         lstart[nl] = lacc;
         *reinterpret_cast<int*>(base + lnk_offset(b->cap)) = nl;
+        nlink[p] = nl;
     }
 }
 
@@ -509,8 +512,8 @@ fp_status upload_tables(fp_batch* b, const std::vector<fp_block>& blocks, const 
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
         b->pending = false;
     }
-    int nblk[2];
-    build_tables(b, blocks, links, b->hstage, nblk);
+    int nblk[2], nlink[2];
+    build_tables(b, blocks, links, b->hstage, nblk, nlink);
     hipError_t e = hipMemcpyAsync(b->dmem, b->hstage, 2 * b->part_bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (batch tables)");
     e = hipEventRecord(b->staged, s);
@@ -518,6 +521,8 @@ fp_status upload_tables(fp_batch* b, const std::vector<fp_block>& blocks, const 
     b->pending = true;
     b->nblk[0] = nblk[0];
     b->nblk[1] = nblk[1];
+    b->nlink[0] = nlink[0];
+    b->nlink[1] = nlink[1];
     return FP_OK;
 }
 
@@ -528,8 +533,9 @@ hipError_t run_batch_step(const fp_batch* b, int mask, hipStream_t s) {
         hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p].nblk,
                            b->tab[p].start, b->tab[p].blk, b->tab[p].cap, ndim);
         for (int k = 0; k < 3; ++k) {
-            hipLaunchKernelGGL(kb_halo, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->lnk_n[p], b->lnk_start[p],
-                               b->lnk[p], b->tab[p].blk, ndim, k);
+            if (mask & (4 << p))
+                hipLaunchKernelGGL(kb_halo, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->lnk_n[p],
+                                   b->lnk_start[p], b->lnk[p], b->tab[p].blk, ndim, k);
             hipError_t e = b->fn[p](b->tab[p], b->sk, k, b->grid[p], -1, s);
             if (e != hipSuccess) return e;
         }
@@ -537,7 +543,9 @@ hipError_t run_batch_step(const fp_batch* b, int mask, hipStream_t s) {
     return hipGetLastError();
 }
 
-int batch_mask(const fp_batch* b) { return (b->nblk[0] > 0 ? 1 : 0) | (b->nblk[1] > 0 ? 2 : 0); }
+int batch_mask(const fp_batch* b) {
+    return (b->nblk[0] > 0 ? 1 : 0) | (b->nblk[1] > 0 ? 2 : 0) | (b->nlink[0] > 0 ? 4 : 0) | (b->nlink[1] > 0 ? 8 : 0);
+}
 
 fp_status check_batch(const fp_batch* b) {
     if (!b) return fail(FP_EINVAL, "batch is NULL");
@@ -1177,7 +1185,7 @@ fp_status fp_batch_profile_step(fp_batch* b, float* kernel_ms, int32_t* kernel_k
         const int ndim = p == 0 ? 2 : 3;
         plan[n][0] = p, plan[n][1] = BK_GHOST, plan[n][2] = -1, ++n;
         for (int k = 0; k < 3; ++k) {
-            plan[n][0] = p, plan[n][1] = 4, plan[n][2] = k, ++n;  // interface exchange
+            if (mask & (4 << p)) plan[n][0] = p, plan[n][1] = 4, plan[n][2] = k, ++n;  // interface exchange
             for (int kind = 0; kind < ndim; ++kind) plan[n][0] = p, plan[n][1] = kind, plan[n][2] = k, ++n;
         }
     }

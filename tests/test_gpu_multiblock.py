@@ -66,7 +66,10 @@ def decompose(case, cuts, Y, recon, prec, steps):
     b = fp.Batch(sc, len(pieces))
     b.set([p[:5] for p in pieces])
     b.set_links(links)
-    b.solve(steps)
+    # one instrumented step first: the exchange runs before every stage
+    kinds = [k for _, k, _ in b.profile_step()]
+    assert kinds.count(4) == 3
+    b.solve(steps - 1)
     torch.cuda.synchronize()
     full = q1.cpu().numpy()
     for Gp, met, q, work, dt, lo in pieces:
