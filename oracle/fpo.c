@@ -594,38 +594,69 @@ double fpo_weno7(const double v[7], double eps)
 /* The polynomial p(x) = sum_k c[k] x^k of degree n-1 whose averages over the
  * unit cells [m-1/2, m+1/2], m = m0 .. m0+n-1, are f[0..n-1] (x measured from
  * the centre of the cell left of the face, unit spacing): the cell-average
- * reconstruction behind every WENO candidate.  Gaussian elimination with
- * partial pivoting, n <= 6. */
-static void cellavg_poly(int n, int m0, const double *f, double *c)
+ * reconstruction behind every WENO candidate.  The averaging matrix
+ * A[r][k] = ((m0+r+1/2)^(k+1) - (m0+r-1/2)^(k+1))/(k+1) depends only on the
+ * stencil, so its inverse is formed once per stencil (Gauss-Jordan with
+ * partial pivoting) and each reconstruction is c = A^-1 f. */
+static void invert_avg(int n, int m0, double inv[6][6])
 {
-    double A[6][7];
+    double A[6][12];
     for (int r = 0; r < n; r++) {
         double lo = m0 + r - 0.5, hi = m0 + r + 0.5;
-        for (int k = 0; k < n; k++)
+        for (int k = 0; k < n; k++) {
             A[r][k] = (pow(hi, k + 1) - pow(lo, k + 1)) / (k + 1);
-        A[r][n] = f[r];
+            A[r][n + k] = r == k ? 1.0 : 0.0;
+        }
     }
     for (int col = 0; col < n; col++) {
         int piv = col;
         for (int r = col + 1; r < n; r++)
             if (fabs(A[r][col]) > fabs(A[piv][col]))
                 piv = r;
-        for (int k = 0; k <= n; k++) {
+        for (int k = 0; k < 2 * n; k++) {
             double t = A[col][k];
             A[col][k] = A[piv][k];
             A[piv][k] = t;
         }
-        for (int r = col + 1; r < n; r++) {
-            double fac = A[r][col] / A[col][col];
-            for (int k = col; k <= n; k++)
+        double d = A[col][col];
+        for (int k = 0; k < 2 * n; k++)
+            A[col][k] /= d;
+        for (int r = 0; r < n; r++) {
+            if (r == col)
+                continue;
+            double fac = A[r][col];
+            for (int k = 0; k < 2 * n; k++)
                 A[r][k] -= fac * A[col][k];
         }
     }
-    for (int r = n - 1; r >= 0; r--) {
-        double s = A[r][n];
-        for (int k = r + 1; k < n; k++)
-            s -= A[r][k] * c[k];
-        c[r] = s / A[r][r];
+    for (int r = 0; r < n; r++)
+        for (int k = 0; k < n; k++)
+            inv[r][k] = A[r][n + k];
+}
+
+/* the inverses of the four quadratic candidates' stencils {k-2 .. k}
+ * (relative to cell i) and of the quintic's {-2 .. 3}; formed on first use */
+static double g_inv3[4][6][6], g_inv6[6][6];
+static int g_inv_ready = 0;
+
+static void cu6_tables(void)
+{
+#pragma omp critical(fpo_cu6_tables)
+    if (!g_inv_ready) {
+        for (int k = 0; k < 4; k++)
+            invert_avg(3, k - 2, g_inv3[k]);
+        invert_avg(6, -2, g_inv6);
+        g_inv_ready = 1;
+    }
+}
+
+static void cellavg_poly(int n, const double inv[6][6], const double *f, double *c)
+{
+    for (int k = 0; k < n; k++) {
+        double s = 0.0;
+        for (int r = 0; r < n; r++)
+            s += inv[k][r] * f[r];
+        c[k] = s;
     }
 }
 
@@ -635,6 +666,12 @@ static double poly_at(int n, const double *c, double x)
     for (int k = n - 1; k >= 0; k--)
         s = s * x + c[k];
     return s;
+}
+
+/* int_{-1/2}^{1/2} x^e dx */
+static double mono_int(int e)
+{
+    return (e % 2) ? 0.0 : 1.0 / ((e + 1) * (double)(1L << e));
 }
 
 /* smoothness of a candidate in the Jiang-Shu sense at unit spacing:
@@ -651,8 +688,7 @@ static double smoothness(int n, const double *c)
             d[k] = (k + 1) * d[k + 1];
         for (int a = 0; a < m; a++)
             for (int b = 0; b < m; b++)
-                if ((a + b) % 2 == 0)
-                    tot += d[a] * d[b] * 2.0 * pow(0.5, a + b + 1) / (a + b + 1);
+                tot += d[a] * d[b] * mono_int(a + b);
     }
     return tot;
 }
@@ -670,24 +706,32 @@ static double smoothness(int n, const double *c)
  * scheme's constants; the paper gives none) and the caller's eps (the paper's
  * WENO epsilon, 1e-6).  Everything here comes from the definitions:
  * reconstruct, evaluate, integrate. */
-void fpo_wenocu6_parts(const double v[6], double q[4], double beta[4])
+/* (the tables must be formed: check_scheme and the public entry points do
+ * it before any parallel region) */
+static void wenocu6_parts(const double v[6], double q[4], double beta[4])
 {
     double c[6];
     for (int k = 0; k < 4; k++) {
-        cellavg_poly(3, k - 2, v + k, c);
+        cellavg_poly(3, g_inv3[k], v + k, c);
         q[k] = poly_at(3, c, 0.5);
         beta[k] = smoothness(3, c);
     }
-    cellavg_poly(6, -2, v, c);
+    cellavg_poly(6, g_inv6, v, c);
     beta[3] = smoothness(6, c);
 }
 
-double fpo_wenocu6(const double v[6], double eps)
+void fpo_wenocu6_parts(const double v[6], double q[4], double beta[4])
+{
+    cu6_tables();
+    wenocu6_parts(v, q, beta);
+}
+
+static double wenocu6(const double v[6], double eps)
 {
     const double d[4] = {1.0 / 20.0, 9.0 / 20.0, 9.0 / 20.0, 1.0 / 20.0};
     const double C = 20.0, qexp = 2.0;
     double q[4], beta[4], alpha[4], asum = 0.0, out = 0.0;
-    fpo_wenocu6_parts(v, q, beta);
+    wenocu6_parts(v, q, beta);
     double tau6 = beta[3] - (beta[0] + 4.0 * beta[1] + beta[2]) / 6.0;
     for (int k = 0; k < 4; k++) {
         alpha[k] = d[k] * pow(C + tau6 / (beta[k] + eps), qexp);
@@ -696,6 +740,12 @@ double fpo_wenocu6(const double v[6], double eps)
     for (int k = 0; k < 4; k++)
         out += alpha[k] / asum * q[k];
     return out;
+}
+
+double fpo_wenocu6(const double v[6], double eps)
+{
+    cu6_tables();
+    return wenocu6(v, eps);
 }
 
 /* half-width of the split-flux stencil below the face node i: the "+" part
@@ -715,7 +765,7 @@ static int recon_width(const fpo_scheme *sc)
 static double reconstruct(const fpo_scheme *sc, const double *v)
 {
     if (sc->recon == 3)
-        return fpo_wenocu6(v, sc->eps);
+        return wenocu6(v, sc->eps);
     if (sc->recon == 2)
         return fpo_weno7(v, sc->eps);
     return sc->recon == 1 ? fpo_linear_upwind5(v) : fpo_weno5(v, sc->eps);
@@ -946,6 +996,8 @@ static int check_scheme(const layout *L, const fpo_scheme *sc)
         return -1;
     if (!(sc->gamma > 1.0) || !(sc->eps > 0.0) || (sc->splitting != 0 && sc->splitting != 1))
         return -1;
+    if (sc->recon == 3)
+        cu6_tables();
     if (sc->mu < 0.0 || (sc->mu > 0.0 && !(sc->prandtl > 0.0)))
         return -1;
     if (sc->mu > 0.0)
