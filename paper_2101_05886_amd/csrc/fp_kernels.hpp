@@ -510,13 +510,12 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
         const int f = k0 - 1 + 4 * it + w;
         if (it + 1 < iters) load_row(tb + W::WIN + 4 * it + w);  // a row of the next iteration
         // this wave's node f: its epilogue operands load while the face is
-        // computed, unless the face computation needs every register (WENO
-        // in FP64)
-        constexpr bool early = !((RECON == 0 || RECON == 3) && PREC == 0);
+        // computed (in FP64 WENO the zeta sweep then spills a few registers,
+        // still faster than waiting for the loads after the face)
         const bool mine = lane_ok && f >= k0 && f < k1;
         const long noff = lb + (long)f * G.sd[DIR];
         EpiPre<NV> pre;
-        if (early && mine) epi_load<NV>(ep, G.vol, noff, pre);
+        if (mine) epi_load<NV>(ep, G.vol, noff, pre);
         double F[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = 0.0;
@@ -535,10 +534,7 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
             double d[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) d[v] = F[v] - prev[v * 64 + lane];
-            if (early)
-                epi_store<NV>(ep, G.vol, noff, pre, d);
-            else
-                epilogue<NV>(ep, G.vol, noff, d);
+            epi_store<NV>(ep, G.vol, noff, pre, d);
         }
         __builtin_amdgcn_s_waitcnt(0);  // this wave's row DMA has landed
         __syncthreads();                // every row of the next iteration is in LDS
