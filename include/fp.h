@@ -257,8 +257,8 @@ fp_status fp_check_state(const fp_grid *grid, const fp_scheme *scheme, const dou
  * launch over a (block, tile) work list of all blocks of a dimensionality;
  * a step is 1 + 3 x ndim such launches (ghost copy, then per stage the
  * sweeps), plus one interface exchange per stage when blocks of that
- * dimensionality are linked, captured once per such configuration into a
- * HIP graph by fp_batch_solve.  Per block the arithmetic is that of fp_rk3_step, and the
+ * dimensionality are linked; fp_batch_solve captures the stages once per
+ * such configuration into a HIP graph and copies the ghosts once per call.  Per block the arithmetic is that of fp_rk3_step, and the
  * result is bitwise the same as advancing the block alone.
  *
  * Ownership: the batch owns its device work-list tables and a pinned host
@@ -293,7 +293,11 @@ fp_status fp_batch_set(fp_batch *batch, const fp_block *blocks, int32_t nblocks,
 /* One RK3 step of every block of the batch. */
 fp_status fp_batch_rk3_step(fp_batch *batch, void *stream);
 
-/* nsteps RK3 steps of every block, replaying the batch's step graph. */
+/* nsteps RK3 steps of every block, replaying the batch's step graph.  The
+ * frozen ghost layers of each block's q are copied into its stage registers
+ * once, at the start of the call (no step writes them; so ghost values the
+ * caller changes take effect at the next call), then the graph, which holds
+ * the stages only, runs nsteps times. */
 fp_status fp_batch_solve(fp_batch *batch, int64_t nsteps, void *stream);
 
 /* Multi-block interfaces.  A link makes the ghost layers of `block` on

@@ -526,12 +526,25 @@ fp_status upload_tables(fp_batch* b, const std::vector<fp_block>& blocks, const 
     return FP_OK;
 }
 
-hipError_t run_batch_step(const fp_batch* b, int mask, hipStream_t s) {
+// the frozen ghost slabs of every block's q into its two stage registers
+void run_batch_ghosts(const fp_batch* b, int mask, hipStream_t s) {
+    for (int p = 0; p < 2; ++p)
+        if (mask & (1 << p))
+            hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p].nblk,
+                               b->tab[p].start, b->tab[p].blk, b->tab[p].cap, p == 0 ? 2 : 3);
+}
+
+// One RK3 step of every block (with the ghost copy first when `ghosts`).
+// Nothing in a step writes the stage registers' frozen ghost slabs (the
+// sweeps write interiors; the interface exchange rewrites its own slabs
+// before every stage), so a run of steps needs the copy only once.
+hipError_t run_batch_step(const fp_batch* b, int mask, hipStream_t s, bool ghosts = true) {
     for (int p = 0; p < 2; ++p) {
         if (!(mask & (1 << p))) continue;
         const int ndim = p == 0 ? 2 : 3;
-        hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p].nblk,
-                           b->tab[p].start, b->tab[p].blk, b->tab[p].cap, ndim);
+        if (ghosts)
+            hipLaunchKernelGGL(kb_frozen_ghosts, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->tab[p].nblk,
+                               b->tab[p].start, b->tab[p].blk, b->tab[p].cap, ndim);
         for (int k = 0; k < 3; ++k) {
             if (mask & (4 << p))
                 hipLaunchKernelGGL(kb_halo, dim3(b->grid[p][BK_GHOST]), dim3(256), 0, s, b->lnk_n[p],
@@ -1058,7 +1071,7 @@ fp_status fp_batch_solve(fp_batch* b, int64_t nsteps, void* stream) {
     if (!b->graph[mask]) {
         e = hipStreamBeginCapture(b->cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = run_batch_step(b, mask, b->cs);
+        hipError_t le = run_batch_step(b, mask, b->cs, false);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(b->cs, &graph);
         if (le != hipSuccess) {
@@ -1072,6 +1085,9 @@ fp_status fp_batch_solve(fp_batch* b, int64_t nsteps, void* stream) {
         if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
         b->graph[mask] = exec;
     }
+    run_batch_ghosts(b, mask, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "fp_batch_solve ghost copy");
     for (int64_t i = 0; i < nsteps; ++i) {
         e = hipGraphLaunch(b->graph[mask], s);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");

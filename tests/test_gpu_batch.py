@@ -242,3 +242,29 @@ def test_c4_full_size_blocks_match_oracle():
             print(f"C4 block {i} {c['n']} variable {v}: {err:.2e}", flush=True)
             assert err <= 1e-12
     b.close()
+
+
+def test_batch_solve_copies_frozen_ghosts_once_per_call():
+    # fp_batch_solve copies the frozen ghost layers at the start of each call;
+    # ghost values the caller changes between calls take effect at the next
+    # call, exactly as with per-step fp_rk3_step (which copies every step)
+    sc = fp.Scheme("weno5", 6, True, precision="mixed")
+    case = G.frozen_case((30, 22, 14), 6, perturb=0.04, seed=21)
+    blk = Block(case, sc)
+    ref_q, ref_w = blk.q.clone(), torch.zeros_like(blk.work)
+    b = fp.Batch(sc, 2)
+    b.set([blk.entry()])
+    b.solve(3)
+    for _ in range(3):
+        fp.rk3_step(blk.grid, sc, blk.met, ref_q, ref_w, blk.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(blk.q, ref_q)
+    g = case["g"]
+    for q in (blk.q, ref_q):  # a new inflow state on the low xi face's ghosts
+        q[:, :, :, :g] *= 1.01
+    b.solve(2)
+    for _ in range(2):
+        fp.rk3_step(blk.grid, sc, blk.met, ref_q, ref_w, blk.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(blk.q, ref_q)
+    b.close()
