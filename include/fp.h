@@ -166,7 +166,10 @@ fp_status fp_rk3_step(const fp_grid *grid, const fp_scheme *scheme, const double
                       double *q, double *work, double dt, void *stream);
 
 /* nsteps RK3 steps of fixed dt.  The first call for a given (grid, scheme,
- * pointers, dt) captures one step into a HIP graph that later calls replay. */
+ * pointers, dt) captures the stages of one step into a HIP graph that later
+ * calls replay; the frozen ghost layers are copied into the stage registers
+ * once per call (no step writes them), so ghost values the caller changes
+ * take effect at the next call. */
 fp_status fp_solve(const fp_grid *grid, const fp_scheme *scheme, const double *met,
                    double *q, double *work, double dt, int64_t nsteps, void *stream);
 

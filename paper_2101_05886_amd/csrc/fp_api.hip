@@ -307,21 +307,26 @@ void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, doub
 // faces, each stage's input gets its ghost layers at the stage time
 // t, t + dt, t + dt/2; with global LF speeds, the work array's tail holds
 // them.
+// the frozen ghost slabs of q into the two stage registers (nothing in a
+// step writes them again, so a run of steps needs this once)
+void launch_frozen(const Ctx& c, const double* q, double* work, hipStream_t s) {
+    bool frozen = false;
+    for (int d = 0; d < c.grid.ndim; ++d) frozen = frozen || c.grid.bc[d] == FP_BC_FROZEN;
+    if (!frozen) return;
+    const long slab = frozen_slab_nodes(c.G, c.grid.ndim);
+    hipLaunchKernelGGL(k_frozen_ghosts, dim3((unsigned)((slab + 255) / 256)), dim3(256), 0, s, c.G,
+                       c.grid.ndim, c.grid.ndim + 2, q, work, work + c.state_elems);
+}
+
 hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, double dt, hipStream_t s,
-                   const BcK* bc = nullptr, double t = 0.0, double* vwork = nullptr) {
+                   const BcK* bc = nullptr, double t = 0.0, double* vwork = nullptr, bool ghosts = true) {
     const bool visc = c.sch.mu > 0.0;
     double* A = work;
     double* B = work + c.state_elems;
     double* R = work + 2 * c.state_elems;
     const double* glf = c.sch.splitting == FP_GLF ? work + 3 * c.state_elems : c.sk.glf;
     const double stage_t[3] = {t, t + dt, t + 0.5 * dt};
-    bool frozen = false;
-    for (int d = 0; d < c.grid.ndim; ++d) frozen = frozen || c.grid.bc[d] == FP_BC_FROZEN;
-    if (frozen) {
-        const long slab = frozen_slab_nodes(c.G, c.grid.ndim);
-        hipLaunchKernelGGL(k_frozen_ghosts, dim3((unsigned)((slab + 255) / 256)), dim3(256), 0, s, c.G,
-                           c.grid.ndim, c.grid.ndim + 2, (const double*)q, A, B);
-    }
+    if (ghosts) launch_frozen(c, q, work, s);
     const double* metV = met + (size_t)(c.grid.ndim == 3 ? 9 : 4) * c.G.vol;
     const double* in[3] = {q, A, B};
     double* out[3] = {A, B, q};
@@ -780,7 +785,7 @@ fp_status fp_solve(const fp_grid* g, const fp_scheme* sch, const double* met, do
             }
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            hipError_t le = run_rk3(c, met, q, work, dt, cs);
+            hipError_t le = run_rk3(c, met, q, work, dt, cs, nullptr, 0.0, nullptr, false);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(cs, &graph);
             if (le != hipSuccess) {
@@ -798,6 +803,9 @@ fp_status fp_solve(const fp_grid* g, const fp_scheme* sch, const double* met, do
             g_graphs[key] = exec;
         }
     }
+    launch_frozen(c, q, work, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "fp_solve ghost copy");
     for (int64_t i = 0; i < nsteps; ++i) {
         e = hipGraphLaunch(exec, s);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");

@@ -268,3 +268,24 @@ def test_batch_solve_copies_frozen_ghosts_once_per_call():
     torch.cuda.synchronize()
     assert torch.equal(blk.q, ref_q)
     b.close()
+
+
+def test_solve_copies_frozen_ghosts_once_per_call():
+    # the single-block fp_solve follows the same rule as the batch
+    sc = fp.Scheme("weno5", 6, True)
+    case = G.frozen_case((26, 20, 12), 6, perturb=0.04, seed=22)
+    blk = Block(case, sc)
+    ref_q, ref_w = blk.q.clone(), torch.zeros_like(blk.work)
+    fp.solve(blk.grid, sc, blk.met, blk.q, blk.work, blk.dt, 3)
+    for _ in range(3):
+        fp.rk3_step(blk.grid, sc, blk.met, ref_q, ref_w, blk.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(blk.q, ref_q)
+    g = case["g"]
+    for q in (blk.q, ref_q):
+        q[:, :, :, :g] *= 1.01
+    fp.solve(blk.grid, sc, blk.met, blk.q, blk.work, blk.dt, 2)
+    for _ in range(2):
+        fp.rk3_step(blk.grid, sc, blk.met, ref_q, ref_w, blk.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(blk.q, ref_q)
