@@ -100,6 +100,12 @@ WORKLOADS = {
                     "200 RK3 steps each; WENO5-JS with 6th-order metrics, FP32-mixed; continuous batching",
                ndim=3, Y=6, recon="weno5", prec="mixed", requests=500, seed=5, load=0.8,
                capacity_requests=100, slots=64, round_steps=10),
+    "dmr": dict(name="2D double Mach reflection (Mach 10, 60 deg), 961x241 nodes on [0,4]x[0,1] with a 5% "
+                     "random grid (seed 11), WENO5-JS with 6th-order metrics and global Lax-Friedrichs "
+                     "splitting, FP64, boundary faces (held inflow, outflow, slip wall, exact moving shock) "
+                     "applied every stage, CFL 0.6 from the initial state",
+                ndim=2, nx=961, ny=241, rand=0.05, Y=6, recon="weno5", prec="fp64", cfl=0.6, seed=11,
+                shock=True),
     "c4": dict(name="48 O-grid sector blocks (seed 4; n_theta 32..192, n_r 32..128, n_z 16..64; wall "
                     "spacing 0.01 stretched x1.1; skew up to 30 deg), uniform Mach 3 along x with frozen "
                     "free-stream ghosts, WENO5-JS with 6th-order metrics, batched: one persistent launch "
@@ -184,6 +190,87 @@ def cpu_baseline_blocks(w, blocks, g, budget_s=20.0):
             "kind": "oracle",
             "sample": f"one RK3 step of each of the first {used} of the {len(blocks)} blocks "
                       f"({nodes} nodes), FP64 oracle (gcc -O2, OpenMP over grid lines), {el:.1f} s"}
+
+
+def bench_dmr(args, w):
+    """The double Mach reflection through fp_solve_bcs: every stage applies
+    the boundary faces and reduces the global LF speeds before its sweeps."""
+    import torch
+    from paper_2101_05886_amd import fp
+    from paper_2101_05886_amd import inputs as I
+    g, Y, nx, ny = 3, w["Y"], w["nx"], w["ny"]
+    xyz = I.dmr_grid(nx, ny, w["rand"], g, Y, w["seed"])
+    nodes = I.state_nodes(xyz, g, Y)
+    q = I.dmr_state(nodes, g)
+    f = I.dmr_faces(nodes, g)
+    dev = torch.device("cuda")
+    G = fp.Grid(2, (nx, ny), g, bc=[fp.FP_BC_FROZEN, fp.FP_BC_FROZEN])
+    S = fp.Scheme(w["recon"], Y, True, splitting="glf")
+    met = fp.metrics(G, Y, torch.from_numpy(xyz).to(dev))
+    bcs = fp.Bcs(f["kind"], mask={k: torch.from_numpy(v).to(dev) for k, v in f["mask"].items()},
+                 nodes=torch.from_numpy(nodes).to(dev), pre=f["pre"], post=f["post"], normal=f["normal"],
+                 offset=f["offset"], speed=f["speed"])
+    qg = torch.from_numpy(q).to(dev)
+    work = torch.zeros(G.work_shape(), dtype=torch.float64, device=dev)
+    dt = float(fp.max_dt(G, S, met, qg, w["cfl"]).item())
+    fp.solve_bcs(G, S, bcs, met, qg, work, 0.0, dt, max(args.warmup, 1))
+    torch.cuda.synchronize()
+    t = max(args.warmup, 1) * dt
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fp.solve_bcs(G, S, bcs, met, qg, work, t, dt, args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    nodes_n = nx * ny
+    value = nodes_n * 3 * args.steps / (ms_total * 1e-3)
+    healthy = int(fp.check_state(G, S, qg).item()) == 0
+    # the sweep kernels with local speeds on the same state: the same kernels
+    # (global speeds only change the operand of their speed floor), timed one
+    # direction per call as the stage launches them
+    SL = fp.Scheme(w["recon"], Y, True)
+    acc = torch.zeros_like(qg)
+    names = ["k_sweep_x", "k_sweep_wg<eta>"]
+    kt = {}
+    for d in range(2):
+        fp.residual_dir(G, SL, met, qg, d, acc, accumulate=d > 0)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.kernel_reps):
+            fp.residual_dir(G, SL, met, qg, d, acc, accumulate=d > 0)
+        b.record()
+        torch.cuda.synchronize()
+        kt[d] = a.elapsed_time(b) / args.kernel_reps
+    dom = max(kt, key=kt.get)
+    out = {
+        "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_total / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "nodes": nodes_n, "metric_order": Y, "recon": w["recon"],
+                   "precision": "fp64", "splitting": "glf", "dt": dt},
+        # no counted flops per face for the 2D kernels: achieved is not claimed
+        "roofline": {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": None, "traffic": None, "kernel": names[dom], "kernel_ms": kt[dom],
+                     "kernel_ms_by_dir": [round(kt[d], 4) for d in range(2)],
+                     "sweeps_share_of_step": 3 * (kt[0] + kt[1]) / (ms_total / args.steps)},
+        "state_ok": healthy,
+    }
+    if not args.no_cpu_baseline:
+        import oracle as O
+        og = O.Grid(2, (nx, ny), g, bc=[1, 1])
+        ob = O.Bcs(f["kind"], mask=f["mask"], nodes=nodes, pre=f["pre"], post=f["post"], normal=f["normal"],
+                   offset=f["offset"], speed=f["speed"])
+        omet = O.metrics(og, Y, xyz)
+        t0 = time.perf_counter()
+        O.solve_bcs(og, O.Scheme(w["recon"], Y, True, splitting="glf"), ob, omet, q, 0.0, dt, 2)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": nodes_n * 3 * 2 / el, "unit": "cell-stage updates/s",
+                               "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"2 RK3 steps of the same grid and state with its boundary faces, "
+                                         f"FP64 oracle, {el:.1f} s"}
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args, w):
@@ -375,6 +462,9 @@ def main():
         return
     if "requests" in w:
         bench_serve(args, w)
+        return
+    if "shock" in w:
+        bench_dmr(args, w)
         return
     xyz, q, g = make_inputs(w)
     ndim, n, Y = w["ndim"], w["n"], w["Y"]

@@ -235,8 +235,11 @@ fp_status fp_apply_bcs(const fp_grid *grid, const fp_bcs *bcs, const double *met
                        double t, void *stream);
 
 /* nsteps RK3 steps from time t0 with the boundary faces applied to each
- * stage's input at the stage's time (t, t + dt, t + dt/2; Sec. 2.2).
- * Launches eagerly (no graph: the stage times change every step). */
+ * stage's input at the stage's time (t, t + dt, t + dt/2, with
+ * t = t0 + i dt at step i; Sec. 2.2).  The first call for a given (grid,
+ * scheme, faces, pointers, dt) captures one step into a HIP graph that later
+ * calls replay: the time lives in the workspace tail, set at the start of
+ * each call and advanced by the graph; fp_release_cache frees the graphs. */
 fp_status fp_solve_bcs(const fp_grid *grid, const fp_scheme *scheme, const fp_bcs *bcs,
                        const double *met, double *q, double *work, double t0, double dt,
                        int64_t nsteps, void *stream);

@@ -286,7 +286,8 @@ hipError_t run_residual(const Ctx& c, const double* met, const double* qs, doubl
 }
 
 // the boundary faces of `qs` at time t: one launch per face that is not held
-void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, double t, hipStream_t s) {
+void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, double t, hipStream_t s,
+                const double* tdev = nullptr) {
     for (int a = 0; a < c.grid.ndim; ++a)
         for (int side = 0; side < 2; ++side) {
             if (bc.kind[a][side] == FP_FACE_HOLD) continue;
@@ -296,9 +297,9 @@ void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, doub
             const long blocks = (total + 255) / 256;
             const dim3 grid((unsigned)(blocks < 1024 ? blocks : 1024));
             if (c.grid.ndim == 3)
-                hipLaunchKernelGGL(k_bc_face<3>, grid, dim3(256), 0, s, c.G, bc, a, side, met, qs, t);
+                hipLaunchKernelGGL(k_bc_face<3>, grid, dim3(256), 0, s, c.G, bc, a, side, met, qs, t, tdev);
             else
-                hipLaunchKernelGGL(k_bc_face<2>, grid, dim3(256), 0, s, c.G, bc, a, side, met, qs, t);
+                hipLaunchKernelGGL(k_bc_face<2>, grid, dim3(256), 0, s, c.G, bc, a, side, met, qs, t, tdev);
         }
 }
 
@@ -318,14 +319,18 @@ void launch_frozen(const Ctx& c, const double* q, double* work, hipStream_t s) {
                        c.grid.ndim, c.grid.ndim + 2, q, work, work + c.state_elems);
 }
 
+// (tdev: the step's start time on the device, then the stage times are
+// *tdev + (0, dt, dt/2) and `t` is ignored)
 hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, double dt, hipStream_t s,
-                   const BcK* bc = nullptr, double t = 0.0, double* vwork = nullptr, bool ghosts = true) {
+                   const BcK* bc = nullptr, double t = 0.0, double* vwork = nullptr, bool ghosts = true,
+                   const double* tdev = nullptr) {
     const bool visc = c.sch.mu > 0.0;
     double* A = work;
     double* B = work + c.state_elems;
     double* R = work + 2 * c.state_elems;
     const double* glf = c.sch.splitting == FP_GLF ? work + 3 * c.state_elems : c.sk.glf;
-    const double stage_t[3] = {t, t + dt, t + 0.5 * dt};
+    const double t0 = tdev ? 0.0 : t;
+    const double stage_t[3] = {t0, t0 + dt, t0 + 0.5 * dt};
     if (ghosts) launch_frozen(c, q, work, s);
     const double* metV = met + (size_t)(c.grid.ndim == 3 ? 9 : 4) * c.G.vol;
     const double* in[3] = {q, A, B};
@@ -333,7 +338,7 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
     const double ca[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
     const double cb[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
     for (int k = 0; k < 3; ++k) {
-        if (bc) launch_bcs(c, *bc, met, const_cast<double*>(in[k]), stage_t[k], s);
+        if (bc) launch_bcs(c, *bc, met, const_cast<double*>(in[k]), stage_t[k], s, tdev);
         if (visc) launch_viscous(c, met, in[k], vwork, R, s);
         EpiK e = epi(EPI_LAST_RK, R);
         e.stage0 = k == 0;
@@ -377,7 +382,28 @@ struct GraphKey {
 
 std::mutex g_mu;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
+
+// step graphs of fp_solve_bcs: the key adds the boundary faces
+struct BcGraphKey {
+    GraphKey k;
+    BcK bc;
+    bool operator<(const BcGraphKey& o) const { return std::memcmp(this, &o, sizeof(BcGraphKey)) < 0; }
+};
+std::map<BcGraphKey, hipGraphExec_t> g_bc_graphs;
+
 std::map<int, hipStream_t> g_capture_streams;
+
+// the stream graphs are captured on, one per device (call with g_mu held)
+hipError_t capture_stream(int dev, hipStream_t* cs) {
+    auto sit = g_capture_streams.find(dev);
+    if (sit != g_capture_streams.end()) {
+        *cs = sit->second;
+        return hipSuccess;
+    }
+    hipError_t e = hipStreamCreateWithFlags(cs, hipStreamNonBlocking);
+    if (e == hipSuccess) g_capture_streams[dev] = *cs;
+    return e;
+}
 
 // ---- batches ----
 
@@ -388,6 +414,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // the workspace tail of the global LF speeds (3 directions x 4 slots)
 constexpr size_t kGlfBytes = 256;
+// the workspace tail's slot (in doubles) of the device time of fp_solve_bcs
+constexpr size_t kTimeSlot = 16;
 
 }  // namespace
 
@@ -775,14 +803,8 @@ fp_status fp_solve(const fp_grid* g, const fp_scheme* sch, const double* met, do
             exec = it->second;
         } else {
             hipStream_t cs;
-            auto sit = g_capture_streams.find(dev);
-            if (sit == g_capture_streams.end()) {
-                e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-                if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
-                g_capture_streams[dev] = cs;
-            } else {
-                cs = sit->second;
-            }
+            e = capture_stream(dev, &cs);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
             hipError_t le = run_rk3(c, met, q, work, dt, cs, nullptr, 0.0, nullptr, false);
@@ -874,9 +896,63 @@ fp_status fp_solve_bcs(const fp_grid* g, const fp_scheme* sch, const fp_bcs* bcs
     if (st) return st;
     st = bind_speeds(c.sk);
     if (st) return st;
+    if (nsteps == 0) return FP_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    double* T = work + 3 * c.state_elems + kTimeSlot;  // {t, t0, steps}
+    BcGraphKey key;
+    std::memset(&key, 0, sizeof key);
+    key.k.dev = dev;
+    key.k.g = *g;
+    key.k.s = *sch;
+    key.k.met = met;
+    key.k.q = q;
+    key.k.work = work;
+    key.k.dt = dt;
+    key.bc = k;
+    hipGraphExec_t exec = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_bc_graphs.find(key);
+        if (it != g_bc_graphs.end()) {
+            exec = it->second;
+        } else {
+            hipStream_t cs;
+            e = capture_stream(dev, &cs);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            hipError_t le = run_rk3(c, met, q, work, dt, cs, &k, 0.0, nullptr, false, T);
+            if (le == hipSuccess) {
+                hipLaunchKernelGGL(k_time_advance, dim3(1), dim3(64), 0, cs, T, dt);
+                le = hipGetLastError();
+            }
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(cs, &graph);
+            if (le != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                return hip_fail(le, "fp_solve_bcs capture");
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+            if (g_bc_graphs.size() >= 64) {
+                for (auto& kv : g_bc_graphs) hipGraphExecDestroy(kv.second);
+                g_bc_graphs.clear();
+            }
+            g_bc_graphs[key] = exec;
+        }
+    }
+    hipLaunchKernelGGL(k_time_set, dim3(1), dim3(64), 0, s, T, t0);
+    launch_frozen(c, q, work, s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "fp_solve_bcs launch");
     for (int64_t i = 0; i < nsteps; ++i) {
-        hipError_t e = run_rk3(c, met, q, work, dt, (hipStream_t)stream, &k, t0 + (double)i * dt);
-        if (e != hipSuccess) return hip_fail(e, "fp_solve_bcs launch");
+        e = hipGraphLaunch(exec, s);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     }
     return FP_OK;
 }
@@ -1263,6 +1339,8 @@ void fp_release_cache(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto& kv : g_graphs) hipGraphExecDestroy(kv.second);
     g_graphs.clear();
+    for (auto& kv : g_bc_graphs) hipGraphExecDestroy(kv.second);
+    g_bc_graphs.clear();
 }
 
 }  // extern "C"

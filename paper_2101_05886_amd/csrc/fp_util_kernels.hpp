@@ -266,7 +266,8 @@ struct BcK {
     double offset, speed;
 };
 
-// The ghost layers l = 1..g of face (a, side) at time t, one thread per
+// The ghost layers l = 1..g of face (a, side) at time t (or *tdev + t when
+// the time lives on the device, as in a captured step), one thread per
 // (boundary node, layer): extrapolation copies the boundary node; the slip
 // wall takes the mirror node l (from the boundary) with the momentum's
 // component along the boundary node's unit metric vector of axis a
@@ -274,7 +275,8 @@ struct BcK {
 template <int DIM>
 __global__ __launch_bounds__(256) void k_bc_face(GeoK G, BcK bc, int a, int side,
                                                   const double* __restrict__ met, double* __restrict__ q,
-                                                  double t) {
+                                                  double t, const double* __restrict__ tdev) {
+    if (tdev) t += *tdev;
     constexpr int NV = DIM + 2, E = NV - 1;
     const int e1 = a == 0 ? 1 : 0, e2 = a == 2 ? 1 : 2;
     const long n1 = G.n[e1], n2 = G.n[e2];
@@ -322,6 +324,24 @@ __global__ __launch_bounds__(256) void k_bc_face(GeoK G, BcK bc, int a, int side
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[v * G.vol + og] = Q[v];
+    }
+}
+
+// The time of a captured step sequence, T = {t, t0, steps}: set before the
+// replays; at the end of every step steps += 1 and t = t0 + steps dt (the
+// step start times of an uncaptured run, without accumulated rounding).
+__global__ void k_time_set(double* T, double t0) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        T[0] = t0;
+        T[1] = t0;
+        T[2] = 0.0;
+    }
+}
+__global__ void k_time_advance(double* T, double dt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double n = T[2] + 1.0;
+        T[2] = n;
+        T[0] = T[1] + n * dt;
     }
 }
 
