@@ -229,8 +229,8 @@ typedef struct {
     double offset, speed;
 } fp_bcs;
 
-/* The ghost layers of q's boundary faces at time t (one launch per face
- * whose kind is not FP_FACE_HOLD). */
+/* The ghost layers of q's boundary faces at time t (one launch over every
+ * face whose kind is not FP_FACE_HOLD). */
 fp_status fp_apply_bcs(const fp_grid *grid, const fp_bcs *bcs, const double *met, double *q,
                        double t, void *stream);
 

@@ -285,22 +285,20 @@ hipError_t run_residual(const Ctx& c, const double* met, const double* qs, doubl
     return c.stage(a, s);
 }
 
-// the boundary faces of `qs` at time t: one launch per face that is not held
+// the boundary faces of `qs` at time t: one launch over every face that is not held
 void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, double t, hipStream_t s,
                 const double* tdev = nullptr) {
+    long total = 0;
     for (int a = 0; a < c.grid.ndim; ++a)
-        for (int side = 0; side < 2; ++side) {
-            if (bc.kind[a][side] == FP_FACE_HOLD) continue;
-            long total = c.G.g;
-            for (int e = 0; e < 3; ++e)
-                if (e != a) total *= c.G.n[e];
-            const long blocks = (total + 255) / 256;
-            const dim3 grid((unsigned)(blocks < 1024 ? blocks : 1024));
-            if (c.grid.ndim == 3)
-                hipLaunchKernelGGL(k_bc_face<3>, grid, dim3(256), 0, s, c.G, bc, a, side, met, qs, t, tdev);
-            else
-                hipLaunchKernelGGL(k_bc_face<2>, grid, dim3(256), 0, s, c.G, bc, a, side, met, qs, t, tdev);
-        }
+        for (int side = 0; side < 2; ++side)
+            if (bc.kind[a][side] != FP_FACE_HOLD) total += bc_face_nodes(c.G, a);
+    if (total == 0) return;
+    const long blocks = (total + 255) / 256;
+    const dim3 grid((unsigned)(blocks < 2048 ? blocks : 2048));
+    if (c.grid.ndim == 3)
+        hipLaunchKernelGGL(k_bc_face<3>, grid, dim3(256), 0, s, c.G, bc, met, qs, t, tdev);
+    else
+        hipLaunchKernelGGL(k_bc_face<2>, grid, dim3(256), 0, s, c.G, bc, met, qs, t, tdev);
 }
 
 // one TVD RK3 step: q -> A -> B -> q with residual accumulator R; the

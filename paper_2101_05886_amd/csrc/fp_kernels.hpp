@@ -594,8 +594,17 @@ __global__ __launch_bounds__(256) void k_glf(GeoK G, double gamma, const double*
     const long sdd = G.sd[d];
     double m0 = 0.0, m1 = 0.0, m2 = 0.0;
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        const int f = (int)(t % nf) - 1;
-        const long r = t / nf;
+        // consecutive threads take consecutive nodes in memory: along the
+        // line for xi, across lines (along i) for eta and zeta
+        int f;
+        long r;
+        if (d == 0) {
+            f = (int)(t % nf) - 1;
+            r = t / nf;
+        } else {
+            r = t % (n1 * n2);
+            f = (int)(t / (n1 * n2)) - 1;
+        }
         const long line = G.base + (r % n1) * G.sd[e1] + (r / n1) * G.sd[e2];
         double Vf = 0.0, sf[DIM];
 #pragma unroll

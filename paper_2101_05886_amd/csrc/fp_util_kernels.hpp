@@ -266,64 +266,99 @@ struct BcK {
     double offset, speed;
 };
 
-// The ghost layers l = 1..g of face (a, side) at time t (or *tdev + t when
-// the time lives on the device, as in a captured step), one thread per
-// (boundary node, layer): extrapolation copies the boundary node; the slip
-// wall takes the mirror node l (from the boundary) with the momentum's
-// component along the boundary node's unit metric vector of axis a
-// reversed; the shock sets post or pre by the side of the moving plane.
+// ghost nodes (boundary nodes x layers) of face (a, side)
+__device__ __host__ __forceinline__ long bc_face_nodes(const GeoK& G, int a) {
+    const int e1 = a == 0 ? 1 : 0, e2 = a == 2 ? 1 : 2;
+    return (long)G.n[e1] * G.n[e2] * G.g;
+}
+
+// Ghost node tt (boundary node fastest, then layer l = 1..g) of face
+// (a, side) at time t: extrapolation copies the boundary node; the slip wall
+// takes the mirror node l (from the boundary) with the momentum's component
+// along the boundary node's unit metric vector of axis a reversed; the shock
+// sets post or pre by the side of the moving plane. Masked nodes are left.
 template <int DIM>
-__global__ __launch_bounds__(256) void k_bc_face(GeoK G, BcK bc, int a, int side,
-                                                  const double* __restrict__ met, double* __restrict__ q,
-                                                  double t, const double* __restrict__ tdev) {
-    if (tdev) t += *tdev;
+__device__ void apply_bc_node(const GeoK& G, const BcK& bc, int a, int side, const double* __restrict__ met,
+                              double* __restrict__ q, double t, long tt) {
     constexpr int NV = DIM + 2, E = NV - 1;
     const int e1 = a == 0 ? 1 : 0, e2 = a == 2 ? 1 : 2;
-    const long n1 = G.n[e1], n2 = G.n[e2];
+    const long n1 = G.n[e1];
     const int g = G.g, kind = bc.kind[a][side], nb = G.n[a];
     const unsigned char* mask = bc.mask[a][side];
-    const long total = n1 * n2 * g, sa = G.sd[a];
-    for (long tt = (long)blockIdx.x * blockDim.x + threadIdx.x; tt < total; tt += (long)gridDim.x * blockDim.x) {
-        const long i1 = tt % n1, r = tt / n1;
-        const int l = (int)(r % g) + 1;
-        const long i2 = r / g;
-        if (mask && !mask[i2 * n1 + i1]) continue;
-        const long line = G.base + i1 * G.sd[e1] + i2 * G.sd[e2];
-        const long og = line + (long)(side ? nb - 1 + l : -l) * sa;
-        double Q[NV];
-        if (kind == 1) {
-            const long os = line + (long)(side ? nb - 1 : 0) * sa;
+    const long sa = G.sd[a];
+    const long i1 = tt % n1, r = tt / n1;
+    const int l = (int)(r % g) + 1;
+    const long i2 = r / g;
+    if (mask && !mask[i2 * n1 + i1]) return;
+    const long line = G.base + i1 * G.sd[e1] + i2 * G.sd[e2];
+    const long og = line + (long)(side ? nb - 1 + l : -l) * sa;
+    double Q[NV];
+    if (kind == 1) {
+        const long os = line + (long)(side ? nb - 1 : 0) * sa;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Q[v] = q[v * G.vol + os];
-        } else if (kind == 2) {
-            const long ob = line + (long)(side ? nb - 1 : 0) * sa;
-            double nw[DIM], nn = 0.0;
+        for (int v = 0; v < NV; ++v) Q[v] = q[v * G.vol + os];
+    } else if (kind == 2) {
+        const long ob = line + (long)(side ? nb - 1 : 0) * sa;
+        double nw[DIM], nn = 0.0;
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                nw[c] = met[(a * DIM + c) * G.vol + ob];
-                nn += nw[c] * nw[c];
-            }
-            nn = sqrt(nn);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) nw[c] /= nn;
-            const long os = line + (long)(side ? nb - 1 - l : l) * sa;
-            double un = 0.0;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) un += nw[c] * q[(1 + c) * G.vol + os];
-            Q[0] = q[os];
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) Q[1 + c] = q[(1 + c) * G.vol + os] - 2.0 * un * nw[c];
-            Q[E] = q[E * G.vol + os];
-        } else {
-            double xn = 0.0;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) xn += bc.normal[c] * bc.nodes[c * G.vol + og];
-            const bool behind = xn < bc.offset + bc.speed * t;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Q[v] = behind ? bc.post[v] : bc.pre[v];
+        for (int c = 0; c < DIM; ++c) {
+            nw[c] = met[(a * DIM + c) * G.vol + ob];
+            nn += nw[c] * nw[c];
         }
+        nn = sqrt(nn);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[v * G.vol + og] = Q[v];
+        for (int c = 0; c < DIM; ++c) nw[c] /= nn;
+        const long os = line + (long)(side ? nb - 1 - l : l) * sa;
+        double un = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) un += nw[c] * q[(1 + c) * G.vol + os];
+        Q[0] = q[os];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) Q[1 + c] = q[(1 + c) * G.vol + os] - 2.0 * un * nw[c];
+        Q[E] = q[E * G.vol + os];
+    } else {
+        double xn = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) xn += bc.normal[c] * bc.nodes[c * G.vol + og];
+        const bool behind = xn < bc.offset + bc.speed * t;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Q[v] = behind ? bc.post[v] : bc.pre[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v * G.vol + og] = Q[v];
+}
+
+// The ghost layers of every face whose kind is not hold, in one launch at
+// time t (or *tdev + t when the time lives on the device, as in a captured
+// step): the ghost nodes of those faces (axis-major, low side first) are
+// numbered one after another, one thread per ghost node.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_bc_face(GeoK G, BcK bc, const double* __restrict__ met,
+                                                  double* __restrict__ q, double t,
+                                                  const double* __restrict__ tdev) {
+    if (tdev) t += *tdev;
+    long total = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int side = 0; side < 2; ++side)
+            if (bc.kind[a][side]) total += bc_face_nodes(G, a);
+    for (long u = (long)blockIdx.x * blockDim.x + threadIdx.x; u < total; u += (long)gridDim.x * blockDim.x) {
+        // the face of ghost node u
+        int a = 0, side = 0;
+        long tt = u;
+        for (int fi = 0; fi < 2 * DIM; ++fi) {
+            const int fa = fi >> 1, fs = fi & 1;
+            if (!bc.kind[fa][fs]) continue;
+            const long cnt = bc_face_nodes(G, fa);
+            if (tt < cnt) {
+                a = fa;
+                side = fs;
+                break;
+            }
+            tt -= cnt;
+        }
+        apply_bc_node<DIM>(G, bc, a, side, met, q, t, tt);
     }
 }
 
