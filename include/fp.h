@@ -119,8 +119,13 @@ size_t fp_state_bytes(const fp_grid *grid);
 size_t fp_metric_bytes(const fp_grid *grid);
 size_t fp_coord_bytes(const fp_grid *grid, int32_t metric_order);
 /* Workspace of fp_rk3_step / fp_solve: three state-sized arrays (two RK
- * stage registers and the residual accumulator) and 256 bytes for the
- * global Lax-Friedrichs speeds.  When an axis is frozen,
+ * stage registers and the residual accumulator) and a 2048-byte tail.  With
+ * global Lax-Friedrichs speeds, RK stage k (0, 1, 2) reduces the speeds of
+ * its input into set k of the tail (direction d's three speeds, for the
+ * classes u_n - c, u_n, u_n + c, at doubles 48 k + 16 d .. 48 k + 16 d + 2)
+ * and zeroes set k + 1 mod 3 for the next stage; each call zeroes set 0
+ * first.  fp_solve_bcs keeps its device time at doubles 144 .. 146.
+ * The tail needs no initial contents.  When an axis is frozen,
  * each step first copies the frozen ghost layers of q into the two stage
  * registers. */
 size_t fp_work_bytes(const fp_grid *grid);

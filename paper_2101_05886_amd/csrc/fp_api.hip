@@ -153,7 +153,7 @@ GeoK make_geo(const fp_grid* g) {
 // The speed floor of local Lax-Friedrichs splitting: zeros in static device
 // memory (zero-initialised, never written), its address fetched once per
 // device with that device current.
-__device__ double g_zero_speeds[16];
+__device__ double g_zero_speeds[3 * kGlfDirStride];
 std::mutex g_zero_mu;
 std::map<int, const double*> g_zero_ptr;
 
@@ -301,11 +301,13 @@ void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, doub
         hipLaunchKernelGGL(k_bc_face<2>, grid, dim3(256), 0, s, c.G, bc, met, qs, t, tdev);
 }
 
-// one TVD RK3 step: q -> A -> B -> q with residual accumulator R; the
-// frozen ghost layers of q are copied into A and B first.  With boundary
-// faces, each stage's input gets its ghost layers at the stage time
-// t, t + dt, t + dt/2; with global LF speeds, the work array's tail holds
-// them.
+// The workspace tail (after the three state-sized arrays): three sets of
+// global LF speeds (RK stage k reduces into set k and zeroes set k + 1 mod 3
+// for the next stage), then the device time of fp_solve_bcs.
+constexpr size_t kGlfBytes = 2048;
+constexpr size_t kTimeSlot = 3 * kGlfSetStride;  // in doubles
+static_assert((kTimeSlot + 3) * sizeof(double) <= kGlfBytes, "the workspace tail is too small");
+
 // the frozen ghost slabs of q into the two stage registers (nothing in a
 // step writes them again, so a run of steps needs this once)
 void launch_frozen(const Ctx& c, const double* q, double* work, hipStream_t s) {
@@ -317,6 +319,21 @@ void launch_frozen(const Ctx& c, const double* q, double* work, hipStream_t s) {
                        c.grid.ndim, c.grid.ndim + 2, q, work, work + c.state_elems);
 }
 
+// what a run of RK steps needs once, before its first step: the frozen
+// ghost layers of the stage registers, and (global LF speeds) the first
+// stage's speed set zeroed
+void launch_run_start(const Ctx& c, const double* q, double* work, hipStream_t s) {
+    launch_frozen(c, q, work, s);
+    if (c.sch.splitting == FP_GLF)
+        hipLaunchKernelGGL(k_glf_reset<2>, dim3(1), dim3(64), 0, s,
+                           reinterpret_cast<unsigned long long*>(work + 3 * c.state_elems));
+}
+
+// One TVD RK3 step: q -> A -> B -> q with residual accumulator R; with
+// `ghosts`, the run-start work (frozen ghost layers of q into A and B, the
+// first speed set zeroed) comes first.  With boundary faces, each stage's
+// input gets its ghost layers at the stage time t, t + dt, t + dt/2; with
+// global LF speeds, stage k reduces into the workspace tail's set k.
 // (tdev: the step's start time on the device, then the stage times are
 // *tdev + (0, dt, dt/2) and `t` is ignored)
 hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, double dt, hipStream_t s,
@@ -326,10 +343,11 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
     double* A = work;
     double* B = work + c.state_elems;
     double* R = work + 2 * c.state_elems;
-    const double* glf = c.sch.splitting == FP_GLF ? work + 3 * c.state_elems : c.sk.glf;
+    const bool glf = c.sch.splitting == FP_GLF;
+    double* sets = work + 3 * c.state_elems;
     const double t0 = tdev ? 0.0 : t;
     const double stage_t[3] = {t0, t0 + dt, t0 + 0.5 * dt};
-    if (ghosts) launch_frozen(c, q, work, s);
+    if (ghosts) launch_run_start(c, q, work, s);
     const double* metV = met + (size_t)(c.grid.ndim == 3 ? 9 : 4) * c.G.vol;
     const double* in[3] = {q, A, B};
     double* out[3] = {A, B, q};
@@ -351,8 +369,11 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
         std::memset(&a, 0, sizeof a);
         a.G = c.G;
         a.sk = c.sk;
-        a.sk.glf = glf;
-        a.glf = c.sch.splitting == FP_GLF;
+        if (glf) {
+            a.sk.glf = sets + kGlfSetStride * k;
+            a.glf_next = sets + kGlfSetStride * ((k + 1) % 3);
+            a.glf = 1;
+        }
         a.met = met;
         a.qs = in[k];
         a.ep_first = epi(visc ? EPI_MID : EPI_FIRST, R);
@@ -410,10 +431,6 @@ constexpr int kSegDefault = 31;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// the workspace tail of the global LF speeds (3 directions x 4 slots)
-constexpr size_t kGlfBytes = 256;
-// the workspace tail's slot (in doubles) of the device time of fp_solve_bcs
-constexpr size_t kTimeSlot = 16;
 
 }  // namespace
 
@@ -823,7 +840,7 @@ fp_status fp_solve(const fp_grid* g, const fp_scheme* sch, const double* met, do
             g_graphs[key] = exec;
         }
     }
-    launch_frozen(c, q, work, s);
+    launch_run_start(c, q, work, s);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "fp_solve ghost copy");
     for (int64_t i = 0; i < nsteps; ++i) {
@@ -945,7 +962,7 @@ fp_status fp_solve_bcs(const fp_grid* g, const fp_scheme* sch, const fp_bcs* bcs
         }
     }
     hipLaunchKernelGGL(k_time_set, dim3(1), dim3(64), 0, s, T, t0);
-    launch_frozen(c, q, work, s);
+    launch_run_start(c, q, work, s);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "fp_solve_bcs launch");
     for (int64_t i = 0; i < nsteps; ++i) {

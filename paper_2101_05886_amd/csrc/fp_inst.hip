@@ -26,7 +26,7 @@ inline unsigned blocks_for(long threads, int per_block) {
 // the scheme constants of direction d's sweep (its global LF speeds)
 inline SchemeK dir_sk(const SchemeK& sk, int d) {
     SchemeK k = sk;
-    k.glf += 4 * d;
+    k.glf += kGlfDirStride * d;
     return k;
 }
 
@@ -38,17 +38,20 @@ void launch_wg(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
                        dim3(256), 0, s, a.G, dir_sk(a.sk, DIR), a.met, a.qs, ep, a.S[DIR]);
 }
 
-// global LF speeds of every direction from the stage input (when asked for)
+// global LF speeds of every direction from the stage input (when asked
+// for), in one launch of at most 128 workgroups of 1024 per direction
 template <int DIM, int Y>
 void launch_glf(const SweepArgs& a, hipStream_t s) {
-    unsigned long long* out = reinterpret_cast<unsigned long long*>(const_cast<double*>(a.sk.glf));
-    hipLaunchKernelGGL(k_glf_reset<DIM>, dim3(1), dim3(64), 0, s, out);
+    unsigned long long* set = reinterpret_cast<unsigned long long*>(const_cast<double*>(a.sk.glf));
+    unsigned long long* next = reinterpret_cast<unsigned long long*>(a.glf_next);
+    long most = 0;
     for (int d = 0; d < DIM; ++d) {
-        long faces = (long)a.G.n[0] * a.G.n[1] * a.G.n[2] / a.G.n[d] * (a.G.n[d] + 1);
-        const long blocks = (faces + 255) / 256;
-        hipLaunchKernelGGL((k_glf<DIM, Y, R == 2 ? 3 : 2>), dim3((unsigned)(blocks < 2048 ? blocks : 2048)),
-                           dim3(256), 0, s, a.G, a.sk.gamma, a.met, a.qs, d, out);
+        const long segs = (long)(a.G.n[d] + kGlfSeg) / kGlfSeg * a.G.n[0] * a.G.n[1] * a.G.n[2] / a.G.n[d];
+        most = segs > most ? segs : most;
     }
+    const long bpd = (most + 1023) / 1024 < 128 ? (most + 1023) / 1024 : 128;
+    hipLaunchKernelGGL((k_glf<DIM, Y, R == 2 ? 3 : 2>), dim3((unsigned)(bpd * DIM)), dim3(1024), 0, s, a.G,
+                       a.sk.gamma, a.met, a.qs, set, next, (int)bpd);
 }
 
 // resident workgroups of a kernel on the current device (queried once)

@@ -566,85 +566,123 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK 
 // global Lax-Friedrichs speeds
 // ---------------------------------------------------------------------------
 
-// Zero the speed slots (3 per direction, 4 apart) before the reductions
-// (a template: this header is compiled into several objects).
+// The speeds live in sets of three directions; direction d of a set takes
+// the three doubles at 16 d (one 128-byte line per direction, so the
+// reductions of different directions do not contend for one line).
+constexpr int kGlfDirStride = 16;
+constexpr int kGlfSetStride = 3 * kGlfDirStride;
+// faces per thread of the reduction (neighbours along the face direction)
+constexpr int kGlfSeg = 2;
+
+// Zero one speed set (a template: this header is compiled into several objects).
 template <int DIM>
-__global__ void k_glf_reset(unsigned long long* out) {
-    if (threadIdx.x < 12) out[threadIdx.x] = 0ull;
+__global__ void k_glf_reset(unsigned long long* set) {
+    if (threadIdx.x < 9) set[kGlfDirStride * (threadIdx.x / 3) + threadIdx.x % 3] = 0ull;
 }
 
-// The largest local Lax-Friedrichs speed over every face of direction d
+// velocity and sound speed of the node at `off`
+template <int DIM>
+__device__ __forceinline__ void glf_node(const double* __restrict__ q, long vol, long off, double gamma,
+                                         double* u, double& cs) {
+    const double rho = q[off];
+    double k2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double mc = q[(1 + c) * vol + off];
+        u[c] = mc / rho;
+        k2 += mc * u[c];
+    }
+    const double p = (gamma - 1.0) * (q[(DIM + 1) * vol + off] - 0.5 * k2);
+    cs = sqrt(gamma * p / rho);
+}
+
+// The largest local Lax-Friedrichs speed over every face of every direction
 // (faces f + 1/2, f = -1 .. n_d - 1, of every interior line), per field class
 // (u_n - c, u_n, u_n + c): at each face the metric vector and 1/J are
 // interpolated (order Y) as for the face's reference state, n = s_f/|s_f|,
 // sigma = |s_f|/(1/J)_f, and the speeds sigma |n . u_m + kappa c_m| are
 // maximised over the stencil nodes m = f - LO .. f + LO + 1.  As in the
 // sweeps, the state's index wraps into the interior on a periodic axis (its
-// ghost layers are not filled) and the metrics are read in place.  One
-// thread per face; the non-negative doubles are reduced as integers (their
-// bit patterns order as the values do).
+// ghost layers are not filled) and the metrics are read in place.
+//
+// Blocks [d bpd, (d + 1) bpd) take direction d.  A thread takes kGlfSeg
+// neighbouring faces of one line and evaluates the velocity and sound speed
+// of each node of their stencils once; consecutive threads take consecutive
+// face pairs along the line for xi and neighbouring lines (contiguous in
+// memory) for eta and zeta.  Each block reduces its maxima and folds them
+// into `set` with one integer atomic max per class (non-negative doubles
+// order as their bit patterns do): few large blocks, since atomics on one
+// cache line serialise.  Block 0 also zeroes `next` (the set the following
+// reduction folds into; NULL: none).
 template <int DIM, int Y, int LO>
-__global__ __launch_bounds__(256) void k_glf(GeoK G, double gamma, const double* __restrict__ met,
-                                              const double* __restrict__ q, int d,
-                                              unsigned long long* __restrict__ out) {
-    constexpr int E = DIM + 1, NMET = DIM == 3 ? 10 : 5;
+__global__ __launch_bounds__(1024) void k_glf(GeoK G, double gamma, const double* __restrict__ met,
+                                              const double* __restrict__ q, unsigned long long* set,
+                                              unsigned long long* next, int bpd) {
+    constexpr int NMET = DIM == 3 ? 10 : 5;
+    constexpr int NW = kGlfSeg + 2 * LO + 1;  // stencil nodes of one segment
+    const int d = blockIdx.x / bpd, bb = blockIdx.x % bpd;
+    if (next && blockIdx.x == 0 && threadIdx.x < 9)
+        next[kGlfDirStride * (threadIdx.x / 3) + threadIdx.x % 3] = 0ull;
     const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
-    const long n1 = G.n[e1], n2 = G.n[e2], nf = G.n[d] + 1;
-    const long total = nf * n1 * n2;
+    const long n1 = G.n[e1], n12 = n1 * G.n[e2];
+    const int nd = G.n[d];
+    const int nseg = (nd + kGlfSeg) / kGlfSeg;  // segments of the n_d + 1 faces of a line
+    const long total = (long)nseg * n12;
     const long sdd = G.sd[d];
+    const bool per = G.bc[d] == 0;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0;
-    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        // consecutive threads take consecutive nodes in memory: along the
-        // line for xi, across lines (along i) for eta and zeta
-        int f;
+    for (long t = (long)bb * blockDim.x + threadIdx.x; t < total; t += (long)bpd * blockDim.x) {
         long r;
+        int sg;
         if (d == 0) {
-            f = (int)(t % nf) - 1;
-            r = t / nf;
+            sg = (int)(t % nseg);
+            r = t / nseg;
         } else {
-            r = t % (n1 * n2);
-            f = (int)(t / (n1 * n2)) - 1;
+            r = t % n12;
+            sg = (int)(t / n12);
         }
+        const int f0 = sg * kGlfSeg - 1;
         const long line = G.base + (r % n1) * G.sd[e1] + (r / n1) * G.sd[e2];
-        double Vf = 0.0, sf[DIM];
+        double u[NW][DIM], cs[NW];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) sf[c] = 0.0;
-#pragma unroll
-        for (int m = 0; m < Y; ++m) {
-            const long off = line + (long)(f - Y / 2 + 1 + m) * sdd;
-            const double w = iw<Y>(m + 4 - Y / 2);
-            Vf += w * met[(NMET - 1) * G.vol + off];
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) sf[c] += w * met[(d * DIM + c) * G.vol + off];
+        for (int j = 0; j < NW; ++j) {
+            // nodes past the last face's stencil are never read: clamp them
+            int p = min(f0 - LO + j, nd + LO);
+            if (per) p = p < 0 ? p + nd : (p >= nd ? p - nd : p);
+            glf_node<DIM>(q, G.vol, line + (long)p * sdd, gamma, u[j], cs[j]);
         }
-        double s2 = 0.0;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) s2 += sf[c] * sf[c];
-        const double sn = sqrt(s2);
-        const double sigma = sn / Vf;
-        double n[DIM];
+        for (int j = 0; j < kGlfSeg; ++j) {
+            const int f = f0 + j;
+            if (f >= nd) break;
+            double Vf = 0.0, sf[DIM];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) n[c] = sf[c] / sn;
-        const int nd = G.n[d];
-        const bool per = G.bc[d] == 0;
+            for (int c = 0; c < DIM; ++c) sf[c] = 0.0;
 #pragma unroll
-        for (int m = -LO; m <= LO + 1; ++m) {
-            int t2 = f + m;
-            if (per) t2 = t2 < 0 ? t2 + nd : (t2 >= nd ? t2 - nd : t2);
-            const long off = line + (long)t2 * sdd;
-            const double rho = q[off];
-            double un = 0.0, k2 = 0.0;
+            for (int m = 0; m < Y; ++m) {
+                const long off = line + (long)(f - Y / 2 + 1 + m) * sdd;
+                const double w = iw<Y>(m + 4 - Y / 2);
+                Vf += w * met[(NMET - 1) * G.vol + off];
 #pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                const double mc = q[(1 + c) * G.vol + off];
-                un += n[c] * mc / rho;
-                k2 += mc * mc / rho;
+                for (int c = 0; c < DIM; ++c) sf[c] += w * met[(d * DIM + c) * G.vol + off];
             }
-            const double p = (gamma - 1.0) * (q[E * G.vol + off] - 0.5 * k2);
-            const double cs = sqrt(gamma * p / rho);
-            m0 = fmax(m0, sigma * fabs(un - cs));
-            m1 = fmax(m1, sigma * fabs(un));
-            m2 = fmax(m2, sigma * fabs(un + cs));
+            double s2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) s2 += sf[c] * sf[c];
+            const double sn = sqrt(s2);
+            const double sigma = sn / Vf;
+            double n[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) n[c] = sf[c] / sn;
+#pragma unroll
+            for (int m = 0; m <= 2 * LO + 1; ++m) {
+                double un = 0.0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) un += n[c] * u[j + m][c];
+                m0 = fmax(m0, sigma * fabs(un - cs[j + m]));
+                m1 = fmax(m1, sigma * fabs(un));
+                m2 = fmax(m2, sigma * fabs(un + cs[j + m]));
+            }
         }
     }
 #pragma unroll
@@ -653,8 +691,8 @@ __global__ __launch_bounds__(256) void k_glf(GeoK G, double gamma, const double*
         m1 = fmax(m1, __shfl_xor(m1, o));
         m2 = fmax(m2, __shfl_xor(m2, o));
     }
-    __shared__ double red[3][4];
-    const int w = threadIdx.x >> 6;
+    __shared__ double red[3][16];
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[0][w] = m0;
         red[1][w] = m1;
@@ -663,8 +701,9 @@ __global__ __launch_bounds__(256) void k_glf(GeoK G, double gamma, const double*
     __syncthreads();
     if (threadIdx.x < 3) {
         const int k = threadIdx.x;
-        const double v = fmax(fmax(red[k][0], red[k][1]), fmax(red[k][2], red[k][3]));
-        atomicMax(out + 4 * d + k, (unsigned long long)__double_as_longlong(v));
+        double v = 0.0;
+        for (int i = 0; i < nw; ++i) v = fmax(v, red[k][i]);
+        atomicMax(set + kGlfDirStride * d + k, (unsigned long long)__double_as_longlong(v));
     }
 }
 
@@ -853,6 +892,7 @@ struct SweepArgs {
     int S[3];
     int nseg[3];
     int glf;  // 1: reduce the global LF speeds of the stage input into sk.glf first
+    double* glf_next;  // the speed set the reduction zeroes for the next stage (or NULL)
 };
 
 // one full residual evaluation (all sweeps) of the given instantiation

@@ -161,11 +161,12 @@ class Grid:
 
     def work_shape(self):
         """the RK3 workspace (see fp_work_bytes), flat: three state-sized
-        arrays and 32 doubles for the global LF speeds"""
+        arrays and a 256-double tail (the global LF speed sets and the
+        device time of solve_bcs)"""
         vol = 1
         for e in self.state_shape():
             vol *= e
-        return (3 * vol + 32,)
+        return (3 * vol + 256,)
 
 
 class Scheme:

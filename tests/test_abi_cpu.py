@@ -33,7 +33,7 @@ def test_sizes():
     n = (16 * 18 * 20)
     assert fp.state_bytes(g) == 8 * 5 * n
     assert fp.metric_bytes(g) == 8 * 10 * n
-    assert fp.work_bytes(g) == 3 * 8 * 5 * n + 256  # + the global LF speeds
+    assert fp.work_bytes(g) == 3 * 8 * 5 * n + 2048  # + the speed sets and the device time
     assert 8 * int(np.prod(g.work_shape())) == fp.work_bytes(g)
     assert fp.coord_bytes(g, 6) == 8 * 3 * (22 * 24 * 26)  # ghost 3 + 3 per side
     g2 = fp.Grid(2, (10, 12), 4)

@@ -124,8 +124,16 @@ def test_glf_rk3_step_matches_the_oracle(recon, Y, g, ndim):
     work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
     fp.rk3_step(fg, fsc, dev(met), qg, work, dt)
     assert relerr(interior(host(qg), g, ndim), interior(ref, g, ndim)) <= 1e-12
-    # the speeds the step used last (its third stage) are the oracle's
-    # global speeds of that stage's input, to rounding
+    # the third stage's speed set (the workspace tail's set 2: doubles
+    # 96 + 16 d .. 98 + 16 d) holds the oracle's global speeds of that
+    # stage's input (the second stage register), to rounding
+    w = host(work)
+    vol = case["q"].size
+    B = w[vol:2 * vol].reshape(case["q"].shape)
+    for d in range(ndim):
+        want = O.glf_speeds(og, osc, met, B, d)
+        got = w[3 * vol + 96 + 16 * d: 3 * vol + 99 + 16 * d]
+        assert np.abs(got - want).max() <= 1e-13 * want.max(), (d, got, want)
     if recon == "weno5" and ndim == 3:
         fsc_m = fp.Scheme(recon, Y, True, precision="mixed", splitting="glf")
         qm = dev(case["q"])
