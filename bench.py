@@ -11,7 +11,9 @@ Default workload (c4): 48 uneven O-grid blocks advanced together by the
 batched path, FP32-mixed reconstruction as `value`, FP64 timed beside it
 (`fp64`, `mixed_over_fp64`), and the serving stream (500 requests, p50/p99
 latency) reported under `serving` (--no-serving skips it).  Single-block
-workloads: --workload c1/c2/c3/c3m; the serving stream alone: --workload c5.
+workloads: --workload c1/c2/c3/c3m/c3w7/c3cu6 and c3v (Navier-Stokes); linked
+blocks: c3x8; the double Mach reflection with its boundary faces: dmr; the
+serving stream alone: --workload c5.
 
 Prints ONE JSON line.  Extra fields: the per-kernel roofline of the dominant
 sweep kernel (timed with HIP events on the stream it runs on), the
@@ -90,6 +92,20 @@ WORKLOADS = {
                       "WENO7-JS with 8th-order metrics, FP32-mixed reconstruction",
                  ndim=3, n=256, Y=8, recon="weno7", prec="mixed", L=12.0, amp=0.1, jitter=0.05,
                  seed=3, mach=0.8, vortex=True, cfl=0.5),
+    "c3cu6": dict(name="3D 256^3 periodic wavy grid (amplitude 0.1, 5% jitter), Mach 0.8 + vortex, "
+                       "WENOCU6 (C = 20, q = 2, eps = 1e-6) with 6th-order metrics, FP32-mixed reconstruction",
+                  ndim=3, n=256, Y=6, recon="wenocu6", prec="mixed", L=12.0, amp=0.1, jitter=0.05,
+                  seed=3, mach=0.8, vortex=True, cfl=0.5, cpu_n=128),
+    "c3v": dict(name="3D 256^3 periodic wavy grid (amplitude 0.1, 5% jitter), Mach 0.8 + vortex, "
+                     "Navier-Stokes: WENO5-JS inviscid fluxes with 6th-order metrics plus sixth-order central "
+                     "viscous fluxes (mu 1e-3, Prandtl 0.72), FP64",
+                ndim=3, n=256, Y=6, recon="weno5", prec="fp64", L=12.0, amp=0.1, jitter=0.05,
+                seed=3, mach=0.8, vortex=True, cfl=0.5, mu=1e-3, prandtl=0.72, cpu_n=128),
+    "c3x8": dict(name="the 256^3 periodic wavy grid (amplitude 0.1, 5% jitter, Mach 0.8 + vortex) cut into "
+                      "2x2x2 blocks of 128^3 joined by interface links on every axis (the outer faces linked "
+                      "around the period), batched, WENO5-JS with 6th-order metrics, FP32-mixed",
+                 ndim=3, n=256, Y=6, recon="weno5", prec="mixed", L=12.0, amp=0.1, jitter=0.05,
+                 seed=3, mach=0.8, vortex=True, cfl=0.5, cuts=(2, 2, 2)),
     "c1": dict(name="2D free stream, 64^2 periodic wavy grid (5% jitter), Mach 0.5 at 20 deg, "
                     "WENO5-JS with 2nd-order metrics, FP64",
                ndim=2, n=64, Y=2, recon="weno5", prec="fp64", L=20.0, amp=0.1, jitter=0.05,
@@ -135,9 +151,15 @@ def cpu_baseline(w, xyz, q, g, budget_s=20.0):
     """FP64 oracle on the host: whole RK3 steps of the same grid and state,
     as many as fit in about budget_s seconds (at least one)."""
     import oracle as O
+    note = ""
+    if "cpu_n" in w:
+        # a slow scheme: the same recipe on a smaller grid keeps the sample short
+        w = dict(w, n=w["cpu_n"])
+        xyz, q, g = make_inputs(w)
+        note = f" (the workload's recipe at {w['n']}^{w['ndim']}: one step at full size takes over a minute)"
     og = O.Grid(w["ndim"], w["n"], g)
     met = O.metrics(og, w["Y"], xyz)
-    sc = O.Scheme(w["recon"], w["Y"], True)
+    sc = O.Scheme(w["recon"], w["Y"], True, mu=w.get("mu", 0.0), prandtl=w.get("prandtl", 0.72))
     dt = O.max_dt(og, sc, met, q, w["cfl"])
     qq = q.copy()
     t0 = time.perf_counter()
@@ -152,7 +174,11 @@ def cpu_baseline(w, xyz, q, g, budget_s=20.0):
     return {"value": nodes * 3 * steps / el, "unit": "cell-stage updates/s", "cores": O.num_threads(),
             "kind": "oracle",
             "sample": f"{steps} full RK3 step(s) of the same {w['n']}^{w['ndim']} grid and state, "
-                      f"FP64 oracle (gcc -O2, OpenMP over grid lines), {el:.1f} s"}
+                      f"FP64 oracle (gcc -O2, OpenMP over grid lines), {el:.1f} s{note}"}
+
+
+def nodes_of(w):
+    return w["n"] ** w["ndim"]
 
 
 def c4_inputs(w):
@@ -270,6 +296,113 @@ def bench_dmr(args, w):
                                "cores": O.num_threads(), "kind": "oracle",
                                "sample": f"2 RK3 steps of the same grid and state with its boundary faces, "
                                          f"FP64 oracle, {el:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
+def event_ms(torch, fn, reps):
+    """mean duration of fn() over reps calls, HIP events on torch's current
+    stream (the stream the library's kernels are launched on), after one
+    untimed call"""
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_links(args, w):
+    """One periodic grid cut into linked blocks, advanced by the batched path:
+    before every stage the interface exchange fills each block's linked ghost
+    slabs from its neighbour's stage register."""
+    import torch
+    from paper_2101_05886_amd import fp
+
+    xyz, q, g = make_inputs(w)
+    n, Y, cuts = w["n"], w["Y"], w["cuts"]
+    gc = g + Y // 2
+    sizes = [n // c for c in cuts]
+    dev = torch.device("cuda")
+    sc = fp.Scheme(w["recon"], Y, True, precision=w["prec"])
+    ent, index = [], {}
+    for c in np.ndindex(*cuts):
+        lo = [c[d] * sizes[d] for d in range(3)]
+        sl_x = (slice(None),) + tuple(slice(lo[d], lo[d] + sizes[d] + 2 * gc) for d in reversed(range(3)))
+        sl_q = (slice(None),) + tuple(slice(lo[d], lo[d] + sizes[d] + 2 * g) for d in reversed(range(3)))
+        G = fp.Grid(3, sizes, g, bc=[fp.FP_BC_FROZEN] * 3)
+        met = fp.metrics(G, Y, torch.from_numpy(np.ascontiguousarray(xyz[sl_x])).to(dev))
+        qg = torch.from_numpy(np.ascontiguousarray(q[sl_q])).to(dev)
+        work = torch.zeros(G.work_shape(), dtype=torch.float64, device=dev)
+        index[c] = len(ent)
+        ent.append([G, met, qg, work, 0.0])
+    dt = min(float(fp.max_dt(e[0], sc, e[1], e[2], w["cfl"]).item()) for e in ent)
+    for e in ent:
+        e[4] = dt
+    links = []
+    for c, i in index.items():
+        for d in range(3):
+            for side in (0, 1):
+                nb = list(c)
+                nb[d] = (c[d] + (1 if side else -1)) % cuts[d]
+                links.append((i, d, side, index[tuple(nb)]))
+    b = fp.Batch(sc, len(ent))
+    b.set([tuple(e) for e in ent])
+    b.set_links(links)
+    seg = b.autotune()
+    b.solve(max(args.warmup, 1))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.solve(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nodes = n ** 3
+    value = nodes * 3 * args.steps / (ms * 1e-3)
+    healthy = all(int(fp.check_state(e[0], sc, e[2]).item()) == 0 for e in ent)
+    kinds = {}
+    for _, kind, t in b.profile_step():
+        kinds.setdefault(kind, []).append(t)
+    pk = {k: sum(v) / len(v) for k, v in kinds.items()}
+    b.close()
+    names = {0: "kb_sweep_x", 1: "kb_sweep_wg<eta>", 2: "kb_sweep_wg<zeta>", 3: "kb_frozen_ghosts",
+             4: "kb_halo"}
+    dom = max((k for k in pk if k < 3), key=pk.get)
+    ftab, fcur = counter_table(FLOPS_FILE)
+    ttab, tcur = counter_table(TRAFFIC_FILE)
+    fpf = ftab.get(f"{w['recon']}/3d/{w['prec']}")
+    traffic = ttab.get(f"c3x8/{names[dom]}") if tcur else None
+    achieved = fpf * nodes / (pk[dom] * 1e-3) / 1e12 if fpf else None
+    peak = PEAK_FP64_TFLOPS if w["prec"] == "fp64" else PEAK_FP32_TFLOPS
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak if achieved else None, "traffic": traffic,
+            "kernel": names[dom], "kernel_ms": pk[dom], "flops_per_face": fpf, "counters_current": fcur,
+            "traffic_gbs": traffic / (pk[dom] * 1e-3) / 1e9 if traffic else None,
+            "kernel_ms_by_kind": {names[k]: round(v, 4) for k, v in sorted(pk.items())}}
+    # the exchange moves g ghost layers of every linked face: NV values read
+    # from the neighbour and written into the block, FP64
+    halo_bytes = len(links) * g * sizes[0] * sizes[1] * 5 * 8 * 2
+    out = {
+        "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if w["prec"] == "fp64" else "f64 state, f32 reconstruction", "data": "synthetic",
+        "config": {"workload": w["name"], "blocks": len(ent), "links": len(links), "nodes": nodes,
+                   "metric_order": Y, "recon": w["recon"], "precision": w["prec"], "segment": seg, "dt": dt},
+        "roofline": roof,
+        "interfaces": {"kernel": "kb_halo", "ms_per_stage": pk.get(4), "bytes_per_stage": halo_bytes,
+                       "achieved_gbs": halo_bytes / (pk[4] * 1e-3) / 1e9 if pk.get(4) else None,
+                       "peak_gbs": PEAK_HBM_GBS},
+        "state_ok": healthy,
+    }
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (FP64 oracle, the undivided grid)")
+        cb = cpu_baseline(w, xyz, q, g)
+        cb["sample"] += " (the undivided grid: the linked blocks reproduce its arithmetic node for node)"
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
@@ -466,23 +599,34 @@ def main():
     if "shock" in w:
         bench_dmr(args, w)
         return
+    if "cuts" in w:
+        bench_links(args, w)
+        return
     xyz, q, g = make_inputs(w)
     ndim, n, Y = w["ndim"], w["n"], w["Y"]
     G = fp.Grid(ndim, n, g)
-    S = fp.Scheme(w["recon"], Y, True, precision=w["prec"])
+    mu = w.get("mu", 0.0)
+    S = fp.Scheme(w["recon"], Y, True, precision=w["prec"], mu=mu, prandtl=w.get("prandtl", 0.72))
+    # the inviscid scheme: the sweep kernels a viscous stage runs are its kernels
+    SI = fp.Scheme(w["recon"], Y, True, precision=w["prec"])
     dev = torch.device("cuda")
     met = fp.metrics(G, Y, torch.from_numpy(xyz).to(dev))
     qg = torch.from_numpy(q).to(dev)
     work = torch.zeros(G.work_shape(), dtype=torch.float64, device=dev)
-    dt = float(fp.max_dt(G, S, met, qg, w["cfl"]).item())
+    dt = float(fp.max_dt(G, SI, met, qg, w["cfl"]).item())
+    if mu > 0:
+        vwork = fp.viscous_work(G)
+        run = lambda k: fp.solve_ns(G, S, met, qg, work, vwork, dt, k)  # noqa: E731
+    else:
+        run = lambda k: fp.solve(G, S, met, qg, work, dt, k)  # noqa: E731
 
     # warmup (captures the step graph), then the timed region
-    fp.solve(G, S, met, qg, work, dt, max(args.warmup, 1))
+    run(max(args.warmup, 1))
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
-    fp.solve(G, S, met, qg, work, dt, args.steps)
+    run(args.steps)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -504,16 +648,32 @@ def main():
     names = ["k_sweep_x", "k_sweep_wg<eta>", "k_sweep_wg<zeta>"]
     kt = {}
     for d in range(ndim):
-        fp.residual_dir(G, S, met, qg, d, acc, accumulate=d > 0)
+        fp.residual_dir(G, SI, met, qg, d, acc, accumulate=d > 0)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(args.kernel_reps):
-            fp.residual_dir(G, S, met, qg, d, acc, accumulate=d > 0)
+            fp.residual_dir(G, SI, met, qg, d, acc, accumulate=d > 0)
         b.record()
         torch.cuda.synchronize()
         kt[d] = a.elapsed_time(b) / args.kernel_reps
     dom = max(kt, key=kt.get)
+    viscous = None
+    if mu > 0:
+        # the viscous part of a residual (node gradients and fluxes, then
+        # their divergence): a viscous residual less the inviscid one
+        dq = torch.zeros_like(qg)
+        t_v = event_ms(torch, lambda: fp.viscous_residual(G, S, met, qg, vwork, dq), args.kernel_reps)
+        t_i = event_ms(torch, lambda: fp.residual(G, SI, met, qg, dq), args.kernel_reps)
+        # algorithmic bytes per node: read q (nv) and the metrics (ndim^2 + 1),
+        # write and read back the ndim (ndim + 1) contravariant fluxes, write
+        # the residual (nv); FP64
+        nv = ndim + 2
+        vb = (nv + ndim * ndim + 1 + 2 * ndim * (ndim + 1) + nv) * 8
+        vms = t_v - t_i
+        viscous = {"kernels": "k_visc_flux + k_visc_div", "ms_per_stage": vms, "bytes_per_node": vb,
+                   "achieved_gbs": vb * nodes_of(w) / (vms * 1e-3) / 1e9 if vms > 0 else None,
+                   "peak_gbs": PEAK_HBM_GBS, "viscous_residual_ms": t_v, "inviscid_residual_ms": t_i}
     ftab, fcur = counter_table(FLOPS_FILE)
     ttab, tcur = counter_table(TRAFFIC_FILE)
     fpf = ftab.get(f"{w['recon']}/{ndim}d/{w['prec']}")
@@ -545,6 +705,9 @@ def main():
                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS},
         "wall_s": wall, "state_ok": healthy,
     }
+    if mu > 0:
+        out["config"].update({"mu": mu, "prandtl": w.get("prandtl", 0.72)})
+        out["viscous"] = viscous
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, xyz, q, g)
     print(json.dumps(out), flush=True)
