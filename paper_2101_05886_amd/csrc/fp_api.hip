@@ -253,8 +253,7 @@ EpiK epi(int mode, double* R) {
 // the node fluxes of `qs` (written to vwork); the sweeps then accumulate
 void launch_viscous(const Ctx& c, const double* met, const double* qs, double* vwork, double* R,
                     hipStream_t s) {
-    const long tot = (long)c.G.n[0] * c.G.n[1] * c.G.n[2];
-    const dim3 grid((unsigned)((tot + 255) / 256));
+    const dim3 grid((unsigned)visc_blocks(c.G.n));
     const double gam = c.sch.gamma, mu = c.sch.mu;
     const double kappa = mu * gam / ((gam - 1.0) * c.sch.prandtl);
     if (c.grid.ndim == 3) {

@@ -384,6 +384,37 @@ __global__ void k_time_advance(double* T, double dt) {
 // viscous fluxes (periodic axes): node fluxes, then their central difference
 // ---------------------------------------------------------------------------
 
+// XCD-aware workgroup order: the dispatcher hands workgroups to the 8 XCDs
+// round-robin (b -> XCD b mod 8), each XCD with its own L2.  Renumbering
+// gives XCD x a contiguous range of the work instead of every eighth item.
+__device__ __forceinline__ long xcd_block(long b, long nb) {
+    const long per = nb / 8, rem = nb % 8, x = b % 8;
+    return x * per + (x < rem ? x : rem) + b / 8;
+}
+
+// The node of this thread in the viscous kernels: a workgroup of 256 takes
+// 64 (i) x 4 (j) nodes of one plane k.  The grid is cut into pencils of
+// 64 x 32 nodes along k; within a pencil the workgroups run through its
+// eight row groups fastest, then k, and each XCD takes a contiguous range of
+// pencils (xcd_block).  A node's neighbours along the second and third axes
+// then lie in the rows and planes its XCD read moments before (about 0.7 MB
+// of L2 back): in plane order, every such neighbour three planes away was an
+// L2 miss, and with one 64 x 4 column per k-run the row neighbours were.
+constexpr int kViscRows = 4, kViscPencil = 8;  // rows per workgroup, row groups per pencil
+__device__ __forceinline__ bool visc_node(const GeoK& G, int (&idx)[3]) {
+    const unsigned L = (unsigned)xcd_block(blockIdx.x, gridDim.x);
+    const unsigned nk = (unsigned)G.n[2], nit = ((unsigned)G.n[0] + 63u) / 64u;
+    const unsigned r = L / kViscPencil, r2 = r / nk;
+    idx[2] = (int)(r % nk);
+    idx[0] = (int)((r2 % nit) * 64u + (threadIdx.x & 63u));
+    idx[1] = (int)(((r2 / nit) * kViscPencil + L % kViscPencil) * kViscRows + (threadIdx.x >> 6));
+    return idx[0] < G.n[0] && idx[1] < G.n[1];
+}
+inline long visc_blocks(const int n[3]) {
+    const int pj = kViscRows * kViscPencil;
+    return (long)((n[0] + 63) / 64) * ((n[1] + pj - 1) / pj) * kViscPencil * n[2];
+}
+
 // sixth-order central first derivative, offsets 1..3 (antisymmetric)
 __device__ __forceinline__ double d6w(int o) { return o == 1 ? 45.0 / 60.0 : (o == 2 ? -9.0 / 60.0 : 1.0 / 60.0); }
 
@@ -421,13 +452,8 @@ __global__ __launch_bounds__(256) void k_visc_flux(GeoK G, double gamma, double 
                                                     const double* __restrict__ met,
                                                     const double* __restrict__ q, double* __restrict__ fv) {
     constexpr int NP = DIM + 1, NMET = DIM == 3 ? 10 : 5;
-    const long tot = (long)G.n[0] * G.n[1] * G.n[2];
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= tot) return;
     int idx[3];
-    idx[0] = (int)(t % G.n[0]);
-    idx[1] = (int)((t / G.n[0]) % G.n[1]);
-    idx[2] = (int)(t / ((long)G.n[0] * G.n[1]));
+    if (!visc_node(G, idx)) return;
     const long o = G.base + idx[0] + idx[1] * G.sd[1] + (long)idx[2] * G.sd[2];
     const double gm1 = gamma - 1.0;
     const double iV = 1.0 / met[(NMET - 1) * G.vol + o];
@@ -490,13 +516,8 @@ __global__ __launch_bounds__(256) void k_visc_flux(GeoK G, double gamma, double 
 template <int DIM>
 __global__ __launch_bounds__(256) void k_visc_div(GeoK G, const double* __restrict__ fv, double* __restrict__ R) {
     constexpr int NP = DIM + 1;
-    const long tot = (long)G.n[0] * G.n[1] * G.n[2];
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= tot) return;
     int idx[3];
-    idx[0] = (int)(t % G.n[0]);
-    idx[1] = (int)((t / G.n[0]) % G.n[1]);
-    idx[2] = (int)(t / ((long)G.n[0] * G.n[1]));
+    if (!visc_node(G, idx)) return;
     const long o = G.base + idx[0] + idx[1] * G.sd[1] + (long)idx[2] * G.sd[2];
     double acc[NP];
 #pragma unroll
