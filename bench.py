@@ -269,6 +269,13 @@ def bench_dmr(args, w):
         torch.cuda.synchronize()
         kt[d] = a.elapsed_time(b) / args.kernel_reps
     dom = max(kt, key=kt.get)
+    ftab, fcur = counter_table(FLOPS_FILE)
+    ttab, tcur = counter_table(TRAFFIC_FILE)
+    fpf = ftab.get(f"{w['recon']}/2d/fp64")
+    traffic = ttab.get(f"dmr/{names[dom]}") if tcur else None
+    # algorithmic units of one launch: the n_d + 1 faces of every line
+    faces = (nx + 1) * ny if dom == 0 else nx * (ny + 1)
+    achieved = fpf * faces / (kt[dom] * 1e-3) / 1e12 if fpf else None
     out = {
         "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_total / args.steps,
@@ -276,9 +283,11 @@ def bench_dmr(args, w):
         "data": "synthetic",
         "config": {"workload": w["name"], "nodes": nodes_n, "metric_order": Y, "recon": w["recon"],
                    "precision": "fp64", "splitting": "glf", "dt": dt},
-        # no counted flops per face for the 2D kernels: achieved is not claimed
-        "roofline": {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": None, "traffic": None, "kernel": names[dom], "kernel_ms": kt[dom],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS if achieved else None, "traffic": traffic,
+                     "kernel": names[dom], "kernel_ms": kt[dom], "flops_per_face": fpf,
+                     "counters_current": fcur,
+                     "traffic_gbs": traffic / (kt[dom] * 1e-3) / 1e9 if traffic else None,
                      "kernel_ms_by_dir": [round(kt[d], 4) for d in range(2)],
                      "sweeps_share_of_step": 3 * (kt[0] + kt[1]) / (ms_total / args.steps)},
         "state_ok": healthy,
