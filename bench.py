@@ -46,7 +46,8 @@ STAGE_BYTES = {3: 560.0 / 3.0, 2: 376.0 / 3.0}
 
 # Floating-point operations per face evaluation of each face kernel, counted
 # from the kernels' instruction mix with rocprofv3 PMC counters (add, mul,
-# transcendental = 1, fma = 2; FP64 plus FP32): profiles/flops_per_face.json,
+# transcendental = 1, fma = 2; FP64 plus FP32), keyed by reconstruction,
+# dimension, precision and metric order: profiles/flops_per_face.json,
 # written from the counter summaries in profiles/.
 FLOPS_FILE = os.path.join(ROOT, "profiles", "flops_per_face.json")
 # HBM bytes per launch of the sweep kernels from FETCH_SIZE / WRITE_SIZE
@@ -271,7 +272,7 @@ def bench_dmr(args, w):
     dom = max(kt, key=kt.get)
     ftab, fcur = counter_table(FLOPS_FILE)
     ttab, tcur = counter_table(TRAFFIC_FILE)
-    fpf = ftab.get(f"{w['recon']}/2d/fp64")
+    fpf = ftab.get(f"{w['recon']}/2d/fp64/m{Y}")
     traffic = ttab.get(f"dmr/{names[dom]}") if tcur else None
     # algorithmic units of one launch: the n_d + 1 faces of every line
     faces = (nx + 1) * ny if dom == 0 else nx * (ny + 1)
@@ -382,7 +383,7 @@ def bench_links(args, w):
     dom = max((k for k in pk if k < 3), key=pk.get)
     ftab, fcur = counter_table(FLOPS_FILE)
     ttab, tcur = counter_table(TRAFFIC_FILE)
-    fpf = ftab.get(f"{w['recon']}/3d/{w['prec']}")
+    fpf = ftab.get(f"{w['recon']}/3d/{w['prec']}/m{Y}")
     traffic = ttab.get(f"c3x8/{names[dom]}") if tcur else None
     achieved = fpf * nodes / (pk[dom] * 1e-3) / 1e12 if fpf else None
     peak = PEAK_FP64_TFLOPS if w["prec"] == "fp64" else PEAK_FP32_TFLOPS
@@ -467,7 +468,7 @@ def bench_batch(args, w):
     dom = max((k for k in pk if k < 3), key=pk.get)
     ftab, fcur = counter_table(FLOPS_FILE)
     ttab, tcur = counter_table(TRAFFIC_FILE)
-    fpf = ftab.get(f"{w['recon']}/3d/mixed")
+    fpf = ftab.get(f"{w['recon']}/3d/mixed/m{w['Y']}")
     traffic = ttab.get(f"c4/{names[dom]}") if tcur else None
     achieved = fpf * nodes / (pk[dom] * 1e-3) / 1e12 if fpf else None
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -685,7 +686,7 @@ def main():
                    "peak_gbs": PEAK_HBM_GBS, "viscous_residual_ms": t_v, "inviscid_residual_ms": t_i}
     ftab, fcur = counter_table(FLOPS_FILE)
     ttab, tcur = counter_table(TRAFFIC_FILE)
-    fpf = ftab.get(f"{w['recon']}/{ndim}d/{w['prec']}")
+    fpf = ftab.get(f"{w['recon']}/{ndim}d/{w['prec']}/m{Y}")
     traffic = ttab.get(f"{args.workload}/{names[dom]}") if tcur else None
     peak = PEAK_FP64_TFLOPS if w["prec"] == "fp64" else PEAK_FP32_TFLOPS
     # algorithmic units of one launch: one face per node (periodic lines)
