@@ -5,10 +5,18 @@ benchmark times.
   metrics: 100 RK3 steps, GPU against the oracle step for step.
 * 3D isentropic vortex, 128^3 wavy grid, linear upwind with sixth-order
   metrics: one full RK3 step against the oracle (every node).
-* 3D 256^3 jittered wavy grid, vortex in a Mach 0.8 flow, WENO5-JS with
-  sixth-order metrics: the residual at sampled nodes (corners and random
-  interior nodes) against the oracle evaluated node by node from the
-  coordinates (the oracle uses no GPU output).
+* 3D 256^3 jittered wavy grid, vortex in a Mach 0.8 flow, WENO5-JS and
+  WENOCU6 with sixth-order metrics: the residual at sampled nodes (corners
+  and random interior nodes) against the oracle evaluated node by node from
+  the coordinates (the oracle uses no GPU output); WENOCU6 also in the
+  FP32-mixed form its benchmark times (bar 1e-4 of the sampled residual's
+  largest value per variable, as for the mixed residual at small sizes).
+* The same grid and state with the sixth-order viscous fluxes (mu 1e-3,
+  Prandtl 0.72): the Navier-Stokes residual at every interior node against
+  the oracle's, both from the oracle's metrics (bars as at small sizes).
+* The same grid cut into 2 x 2 x 2 linked 128^3 blocks, advanced by the
+  batched path as its benchmark runs it (FP32-mixed, autotuned segments):
+  bitwise the single 256^3 block after two RK3 steps.
 
 Tolerances.  The symmetric conservative metrics difference products of
 coordinates (size |x|) into metrics of size h^2 (h the node spacing), so two
@@ -108,7 +116,8 @@ def test_c2_vortex_128_full_rk3_step(Y):
     assert relerr(interior(host(qg), g, 3), interior(ref, g, 3)) <= 20 * metric_tol(xyz, n, L)
 
 
-def test_c3_256_sampled_residual_and_metrics():
+@pytest.mark.parametrize("recon", ["weno5", "wenocu6"])
+def test_c3_256_sampled_residual_and_metrics(recon):
     n, g, Y, L = 256, 3, 6, 12.0
     xyz = I.wavy_grid(3, n, L, g, Y, amp=0.1, jitter=0.05, seed=3)
     vel = I.mach_velocity(0.8, I.direction_3d())
@@ -126,10 +135,15 @@ def test_c3_256_sampled_residual_and_metrics():
     assert np.abs(got_m[:, 9] - ref_m[:, 9]).max() <= tol * np.abs(ref_m[:, 9]).max()
     del met_h
     qg = dev(q)
-    r = host(fp.residual(fg, fp.Scheme("weno5", Y, True), mg, qg))
+    r = host(fp.residual(fg, fp.Scheme(recon, Y, True), mg, qg))
     got = np.array([r[:, g + p[2], g + p[1], g + p[0]] for p in pts])
     del r
-    ref = O.residual_at_xyz(og, O.Scheme("weno5", Y, True), xyz, q, pts)
+    ref = O.residual_at_xyz(og, O.Scheme(recon, Y, True), xyz, q, pts)
+    if recon == "wenocu6":
+        r = host(fp.residual(fg, fp.Scheme(recon, Y, True, precision="mixed"), mg, qg))
+        got_m = np.array([r[:, g + p[2], g + p[1], g + p[0]] for p in pts])
+        del r
+        assert np.all(np.abs(got_m - ref).max(axis=0) <= 1e-4 * np.abs(ref).max(axis=0))
     # CFL 0.5 step from the oracle metrics at the sampled nodes
     speed = 0.0
     for p, m in zip(pts, ref_m):
@@ -142,3 +156,72 @@ def test_c3_256_sampled_residual_and_metrics():
     # end to end (each side its own metrics): bounded by the metric bar
     qscale = np.abs(q.reshape(5, -1)).max(axis=1)
     assert np.all(dt * np.abs(got - ref).max(axis=0) <= max(1e-12, 20 * tol) * qscale)
+
+
+def c3_grid_and_state(n=256, g=3, Y=6, L=12.0):
+    xyz = I.wavy_grid(3, n, L, g, Y, amp=0.1, jitter=0.05, seed=3)
+    vel = I.mach_velocity(0.8, I.direction_3d())
+    q = I.Vortex(vel_inf=tuple(vel)).state(I.state_nodes(xyz, g, Y), period=L)
+    return xyz, q
+
+
+def test_c3v_256_navier_stokes_residual_every_node():
+    n, g, Y = 256, 3, 6
+    mu, pr = 1e-3, 0.72
+    xyz, q = c3_grid_and_state(n, g, Y)
+    og, fg = O.Grid(3, n, g), fp.Grid(3, n, g)
+    met = O.metrics(og, Y, xyz)
+    del xyz
+    ref = O.residual(og, O.Scheme("weno5", Y, True, mu=mu, prandtl=pr), met, q)
+    mg, qg = dev(met), dev(q)
+    got = host(fp.viscous_residual(fg, fp.Scheme("weno5", Y, True, mu=mu, prandtl=pr), mg, qg,
+                                   fp.viscous_work(fg)))
+    assert relerr(interior(got, g, 3), interior(ref, g, 3)) <= 1e-11
+    # the viscous part itself (the residual less the inviscid one)
+    ref -= O.residual(og, O.Scheme("weno5", Y, True), met, q)
+    got -= host(fp.residual(fg, fp.Scheme("weno5", Y, True), mg, qg))
+    assert relerr(interior(got, g, 3)[1:], interior(ref, g, 3)[1:]) <= 1e-9
+
+
+def test_c3x8_linked_blocks_bitwise_the_single_block():
+    n, g, Y, steps = 256, 3, 6, 2
+    xyz, q = c3_grid_and_state(n, g, Y)
+    sc = fp.Scheme("weno5", Y, True, precision="mixed")
+    G1 = fp.Grid(3, n, g)
+    m1 = fp.metrics(G1, Y, dev(xyz))
+    q1 = dev(q)
+    dt = float(fp.max_dt(G1, sc, m1, q1, 0.5).item())
+    w1 = torch.zeros(G1.work_shape(), dtype=torch.float64, device="cuda")
+    fp.solve(G1, sc, m1, q1, w1, dt, steps)
+    full = host(q1)
+    del m1, q1, w1
+    torch.cuda.empty_cache()
+    h, gc = n // 2, g + Y // 2
+    ents, index, los = [], {}, []
+    for c in np.ndindex(2, 2, 2):
+        lo = [c[d] * h for d in range(3)]
+        sl_x = (slice(None),) + tuple(slice(lo[d], lo[d] + h + 2 * gc) for d in reversed(range(3)))
+        sl_q = (slice(None),) + tuple(slice(lo[d], lo[d] + h + 2 * g) for d in reversed(range(3)))
+        Gp = fp.Grid(3, (h, h, h), g, bc=[fp.FP_BC_FROZEN] * 3)
+        index[c] = len(ents)
+        ents.append((Gp, fp.metrics(Gp, Y, dev(xyz[sl_x])), dev(q[sl_q]),
+                     torch.zeros(Gp.work_shape(), dtype=torch.float64, device="cuda"), dt))
+        los.append(lo)
+    links = []
+    for c, i in index.items():
+        for d in range(3):
+            for side in (0, 1):
+                nb = list(c)
+                nb[d] = (c[d] + (1 if side else -1)) % 2
+                links.append((i, d, side, index[tuple(nb)]))
+    b = fp.Batch(sc, len(ents))
+    b.set(ents)
+    b.set_links(links)
+    b.autotune()
+    b.solve(steps)
+    torch.cuda.synchronize()
+    for (Gp, met, qp, work, _), lo in zip(ents, los):
+        got = interior(host(qp), g, 3)
+        want = full[(slice(None),) + tuple(slice(g + lo[d], g + lo[d] + h) for d in reversed(range(3)))]
+        assert np.array_equal(got, want), f"block at {lo}: max diff {np.abs(got - want).max():.3e}"
+    b.close()
