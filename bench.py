@@ -182,6 +182,16 @@ def nodes_of(w):
     return w["n"] ** w["ndim"]
 
 
+def profiled_kinds(fp, G, S, met, qg, work, dt, steps, bcs=None, t=0.0, vwork=None):
+    """mean duration (ms) per launch kind over `steps` instrumented RK3 steps
+    (fp_profile_step: every launch of the step followed by a HIP event)"""
+    acc = {}
+    for i in range(max(1, steps)):
+        for kind, ms in fp.profile_step(G, S, met, qg, work, dt, bcs=bcs, t=t + i * dt, vwork=vwork):
+            acc.setdefault(kind, []).append(ms)
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
 def c4_inputs(w):
     """coordinates and states of the 48 O-grid blocks (host arrays)"""
     from paper_2101_05886_amd import inputs as I
@@ -252,23 +262,12 @@ def bench_dmr(args, w):
     nodes_n = nx * ny
     value = nodes_n * 3 * args.steps / (ms_total * 1e-3)
     healthy = int(fp.check_state(G, S, qg).item()) == 0
-    # the sweep kernels with local speeds on the same state: the same kernels
-    # (global speeds only change the operand of their speed floor), timed one
-    # direction per call as the stage launches them
-    SL = fp.Scheme(w["recon"], Y, True)
-    acc = torch.zeros_like(qg)
+    # per-launch durations of instrumented steps of the same run (boundary
+    # faces, global speeds and sweeps of every stage), after the timed region
     names = ["k_sweep_x", "k_sweep_wg<eta>"]
-    kt = {}
-    for d in range(2):
-        fp.residual_dir(G, SL, met, qg, d, acc, accumulate=d > 0)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(args.kernel_reps):
-            fp.residual_dir(G, SL, met, qg, d, acc, accumulate=d > 0)
-        b.record()
-        torch.cuda.synchronize()
-        kt[d] = a.elapsed_time(b) / args.kernel_reps
+    t_end = t + args.steps * dt
+    per_kind = profiled_kinds(fp, G, S, met, qg, work, dt, args.kernel_reps, bcs=bcs, t=t_end)
+    kt = {d: per_kind[d] for d in range(2)}
     dom = max(kt, key=kt.get)
     ftab, fcur = counter_table(FLOPS_FILE)
     ttab, tcur = counter_table(TRAFFIC_FILE)
@@ -290,6 +289,7 @@ def bench_dmr(args, w):
                      "counters_current": fcur,
                      "traffic_gbs": traffic / (kt[dom] * 1e-3) / 1e9 if traffic else None,
                      "kernel_ms_by_dir": [round(kt[d], 4) for d in range(2)],
+                     "glf_ms_per_stage": per_kind.get(5), "bc_faces_ms_per_stage": per_kind.get(6),
                      "sweeps_share_of_step": 3 * (kt[0] + kt[1]) / (ms_total / args.steps)},
         "state_ok": healthy,
     }
@@ -307,21 +307,6 @@ def bench_dmr(args, w):
                                "sample": f"2 RK3 steps of the same grid and state with its boundary faces, "
                                          f"FP64 oracle, {el:.1f} s"}
     print(json.dumps(out), flush=True)
-
-
-def event_ms(torch, fn, reps):
-    """mean duration of fn() over reps calls, HIP events on torch's current
-    stream (the stream the library's kernels are launched on), after one
-    untimed call"""
-    fn()
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        fn()
-    b.record()
-    torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
 
 
 def bench_links(args, w):
@@ -650,40 +635,26 @@ def main():
     torch.cuda.synchronize()
     healthy = int(flag.item()) == 0
 
-    # per-kernel timing of the three sweep kernels an RK stage runs, one
-    # kernel per call with the stage's launch configuration (fp_residual_dir
-    # launches exactly the stage's kernel of that direction), HIP events on
-    # torch's current stream, which is the stream the kernels are launched on
-    acc = torch.zeros_like(qg)
+    # per-launch durations of instrumented RK3 steps run right after the
+    # timed region: the same launches the step graph replays, each followed
+    # by a HIP event on the stream the kernels run on
     names = ["k_sweep_x", "k_sweep_wg<eta>", "k_sweep_wg<zeta>"]
-    kt = {}
-    for d in range(ndim):
-        fp.residual_dir(G, SI, met, qg, d, acc, accumulate=d > 0)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(args.kernel_reps):
-            fp.residual_dir(G, SI, met, qg, d, acc, accumulate=d > 0)
-        b.record()
-        torch.cuda.synchronize()
-        kt[d] = a.elapsed_time(b) / args.kernel_reps
+    per_kind = profiled_kinds(fp, G, S, met, qg, work, dt, args.kernel_reps,
+                              vwork=vwork if mu > 0 else None)
+    kt = {d: per_kind[d] for d in range(ndim)}
     dom = max(kt, key=kt.get)
     viscous = None
     if mu > 0:
-        # the viscous part of a residual (node gradients and fluxes, then
-        # their divergence): a viscous residual less the inviscid one
-        dq = torch.zeros_like(qg)
-        t_v = event_ms(torch, lambda: fp.viscous_residual(G, S, met, qg, vwork, dq), args.kernel_reps)
-        t_i = event_ms(torch, lambda: fp.residual(G, SI, met, qg, dq), args.kernel_reps)
-        # algorithmic bytes per node: read q (nv) and the metrics (ndim^2 + 1),
-        # write and read back the ndim (ndim + 1) contravariant fluxes, write
-        # the residual (nv); FP64
+        # the viscous part of a stage (node fluxes, then their divergence)
+        # against its algorithmic bytes per node: read q (nv) and the metrics
+        # (ndim^2 + 1), write and read back the ndim (ndim + 1) contravariant
+        # fluxes, write the residual (nv); FP64
         nv = ndim + 2
         vb = (nv + ndim * ndim + 1 + 2 * ndim * (ndim + 1) + nv) * 8
-        vms = t_v - t_i
-        viscous = {"kernels": "k_visc_flux + k_visc_div", "ms_per_stage": vms, "bytes_per_node": vb,
-                   "achieved_gbs": vb * nodes_of(w) / (vms * 1e-3) / 1e9 if vms > 0 else None,
-                   "peak_gbs": PEAK_HBM_GBS, "viscous_residual_ms": t_v, "inviscid_residual_ms": t_i}
+        vms = per_kind[7] + per_kind[8]
+        viscous = {"kernels": "k_visc_flux + k_visc_div", "ms_per_stage": vms,
+                   "k_visc_flux_ms": per_kind[7], "k_visc_div_ms": per_kind[8], "bytes_per_node": vb,
+                   "achieved_gbs": vb * nodes_of(w) / (vms * 1e-3) / 1e9, "peak_gbs": PEAK_HBM_GBS}
     ftab, fcur = counter_table(FLOPS_FILE)
     ttab, tcur = counter_table(TRAFFIC_FILE)
     fpf = ftab.get(f"{w['recon']}/{ndim}d/{w['prec']}/m{Y}")

@@ -249,6 +249,25 @@ fp_status fp_solve_bcs(const fp_grid *grid, const fp_scheme *scheme, const fp_bc
                        const double *met, double *q, double *work, double t0, double dt,
                        int64_t nsteps, void *stream);
 
+/* Instrumented step (a measurement aid; none of the paper's operations is
+ * added): one RK3 step of q (Sec. 2.2) exactly as fp_rk3_step launches it,
+ * with the boundary faces of fp_solve_bcs at the stage times of a step from
+ * t when bcs is non-NULL, and with the viscous part of fp_solve_ns when
+ * scheme->mu > 0 (vwork then required, else ignored), and a HIP event
+ * recorded on `stream` before the first launch and after each launch.
+ * Synchronises, then writes each launch's duration in milliseconds to
+ * kernel_ms[i] and its kind to kernel_kind[i], in launch order:
+ *   0 xi sweep, 1 eta sweep, 2 zeta sweep, 3 frozen-ghost copy,
+ *   5 global Lax-Friedrichs speeds, 6 boundary faces, 7 viscous node fluxes,
+ *   8 viscous divergence, 9 reset of the first speed set;
+ * and the number of launches (at most 32) to *n_kernels.  q advances one
+ * step; work (and vwork) as for the step.  FP_EINVAL if max_kernels < 32 or
+ * an argument is invalid (nothing enqueued then). */
+fp_status fp_profile_step(const fp_grid *grid, const fp_scheme *scheme, const fp_bcs *bcs,
+                          const double *met, double *q, double *work, double *vwork, double t,
+                          double dt, float *kernel_ms, int32_t *kernel_kind, int32_t max_kernels,
+                          int32_t *n_kernels, void *stream);
+
 /* dt = cfl / max_i sum_d (|s_d . u| + c |s_d|) (1/J)^{-1} over the interior
  * (the convective CFL limit), written to dt_dev (device, one double). */
 fp_status fp_max_dt(const fp_grid *grid, const fp_scheme *scheme, const double *met,

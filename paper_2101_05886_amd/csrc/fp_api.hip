@@ -252,17 +252,20 @@ EpiK epi(int mode, double* R) {
 // the viscous part of the residual accumulator: R = sum_d D6_d(Fv~_d) from
 // the node fluxes of `qs` (written to vwork); the sweeps then accumulate
 void launch_viscous(const Ctx& c, const double* met, const double* qs, double* vwork, double* R,
-                    hipStream_t s) {
+                    hipStream_t s, Probe* probe = nullptr) {
     const dim3 grid((unsigned)visc_blocks(c.G.n));
     const double gam = c.sch.gamma, mu = c.sch.mu;
     const double kappa = mu * gam / ((gam - 1.0) * c.sch.prandtl);
-    if (c.grid.ndim == 3) {
+    if (c.grid.ndim == 3)
         hipLaunchKernelGGL(k_visc_flux<3>, grid, dim3(256), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
-        hipLaunchKernelGGL(k_visc_div<3>, grid, dim3(256), 0, s, c.G, (const double*)vwork, R);
-    } else {
+    else
         hipLaunchKernelGGL(k_visc_flux<2>, grid, dim3(256), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
+    probe_mark(probe, PK_VFLUX, s);
+    if (c.grid.ndim == 3)
+        hipLaunchKernelGGL(k_visc_div<3>, grid, dim3(256), 0, s, c.G, (const double*)vwork, R);
+    else
         hipLaunchKernelGGL(k_visc_div<2>, grid, dim3(256), 0, s, c.G, (const double*)vwork, R);
-    }
+    probe_mark(probe, PK_VDIV, s);
 }
 
 // one residual evaluation; the last sweep applies `last`; with a viscous
@@ -286,7 +289,7 @@ hipError_t run_residual(const Ctx& c, const double* met, const double* qs, doubl
 
 // the boundary faces of `qs` at time t: one launch over every face that is not held
 void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, double t, hipStream_t s,
-                const double* tdev = nullptr) {
+                const double* tdev = nullptr, Probe* probe = nullptr) {
     long total = 0;
     for (int a = 0; a < c.grid.ndim; ++a)
         for (int side = 0; side < 2; ++side)
@@ -298,34 +301,41 @@ void launch_bcs(const Ctx& c, const BcK& bc, const double* met, double* qs, doub
         hipLaunchKernelGGL(k_bc_face<3>, grid, dim3(256), 0, s, c.G, bc, met, qs, t, tdev);
     else
         hipLaunchKernelGGL(k_bc_face<2>, grid, dim3(256), 0, s, c.G, bc, met, qs, t, tdev);
+    probe_mark(probe, PK_BC, s);
 }
 
 // The workspace tail (after the three state-sized arrays): three sets of
 // global LF speeds (RK stage k reduces into set k and zeroes set k + 1 mod 3
 // for the next stage), then the device time of fp_solve_bcs.
 constexpr size_t kGlfBytes = 2048;
+// launches of one instrumented step, at most: run start (2) + 3 stages x
+// (boundary faces, 2 viscous, speeds, 3 sweeps)
+constexpr int kProfileMax = 32;
 constexpr size_t kTimeSlot = 3 * kGlfSetStride;  // in doubles
 static_assert((kTimeSlot + 3) * sizeof(double) <= kGlfBytes, "the workspace tail is too small");
 
 // the frozen ghost slabs of q into the two stage registers (nothing in a
 // step writes them again, so a run of steps needs this once)
-void launch_frozen(const Ctx& c, const double* q, double* work, hipStream_t s) {
+void launch_frozen(const Ctx& c, const double* q, double* work, hipStream_t s, Probe* probe = nullptr) {
     bool frozen = false;
     for (int d = 0; d < c.grid.ndim; ++d) frozen = frozen || c.grid.bc[d] == FP_BC_FROZEN;
     if (!frozen) return;
     const long slab = frozen_slab_nodes(c.G, c.grid.ndim);
     hipLaunchKernelGGL(k_frozen_ghosts, dim3((unsigned)((slab + 255) / 256)), dim3(256), 0, s, c.G,
                        c.grid.ndim, c.grid.ndim + 2, q, work, work + c.state_elems);
+    probe_mark(probe, PK_GHOST, s);
 }
 
 // what a run of RK steps needs once, before its first step: the frozen
 // ghost layers of the stage registers, and (global LF speeds) the first
 // stage's speed set zeroed
-void launch_run_start(const Ctx& c, const double* q, double* work, hipStream_t s) {
-    launch_frozen(c, q, work, s);
-    if (c.sch.splitting == FP_GLF)
+void launch_run_start(const Ctx& c, const double* q, double* work, hipStream_t s, Probe* probe = nullptr) {
+    launch_frozen(c, q, work, s, probe);
+    if (c.sch.splitting == FP_GLF) {
         hipLaunchKernelGGL(k_glf_reset<2>, dim3(1), dim3(64), 0, s,
                            reinterpret_cast<unsigned long long*>(work + 3 * c.state_elems));
+        probe_mark(probe, PK_GLF_RESET, s);
+    }
 }
 
 // One TVD RK3 step: q -> A -> B -> q with residual accumulator R; with
@@ -337,7 +347,7 @@ void launch_run_start(const Ctx& c, const double* q, double* work, hipStream_t s
 // *tdev + (0, dt, dt/2) and `t` is ignored)
 hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, double dt, hipStream_t s,
                    const BcK* bc = nullptr, double t = 0.0, double* vwork = nullptr, bool ghosts = true,
-                   const double* tdev = nullptr) {
+                   const double* tdev = nullptr, Probe* probe = nullptr) {
     const bool visc = c.sch.mu > 0.0;
     double* A = work;
     double* B = work + c.state_elems;
@@ -346,15 +356,15 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
     double* sets = work + 3 * c.state_elems;
     const double t0 = tdev ? 0.0 : t;
     const double stage_t[3] = {t0, t0 + dt, t0 + 0.5 * dt};
-    if (ghosts) launch_run_start(c, q, work, s);
+    if (ghosts) launch_run_start(c, q, work, s, probe);
     const double* metV = met + (size_t)(c.grid.ndim == 3 ? 9 : 4) * c.G.vol;
     const double* in[3] = {q, A, B};
     double* out[3] = {A, B, q};
     const double ca[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
     const double cb[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
     for (int k = 0; k < 3; ++k) {
-        if (bc) launch_bcs(c, *bc, met, const_cast<double*>(in[k]), stage_t[k], s, tdev);
-        if (visc) launch_viscous(c, met, in[k], vwork, R, s);
+        if (bc) launch_bcs(c, *bc, met, const_cast<double*>(in[k]), stage_t[k], s, tdev, probe);
+        if (visc) launch_viscous(c, met, in[k], vwork, R, s, probe);
         EpiK e = epi(EPI_LAST_RK, R);
         e.stage0 = k == 0;
         e.out = out[k];
@@ -375,6 +385,7 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
         }
         a.met = met;
         a.qs = in[k];
+        a.probe = probe;
         a.ep_first = epi(visc ? EPI_MID : EPI_FIRST, R);
         a.ep_mid = epi(EPI_MID, R);
         a.ep_last = e;
@@ -968,6 +979,47 @@ fp_status fp_solve_bcs(const fp_grid* g, const fp_scheme* sch, const fp_bcs* bcs
         e = hipGraphLaunch(exec, s);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     }
+    return FP_OK;
+}
+
+fp_status fp_profile_step(const fp_grid* g, const fp_scheme* sch, const fp_bcs* bcs, const double* met,
+                          double* q, double* work, double* vwork, double t, double dt, float* kernel_ms,
+                          int32_t* kernel_kind, int32_t max_kernels, int32_t* n_kernels, void* stream) {
+    Ctx c;
+    fp_status st = make_ctx(g, sch, c);
+    if (st) return st;
+    if (!met || !q || !work || (sch->mu > 0.0 && !vwork)) return fail(FP_EINVAL, "NULL array");
+    if (!kernel_ms || !kernel_kind || !n_kernels) return fail(FP_EINVAL, "NULL output");
+    if (max_kernels < kProfileMax) return fail(FP_EINVAL, "max_kernels must be >= %d", kProfileMax);
+    if (!(dt > 0.0)) return fail(FP_EINVAL, "dt must be positive");
+    BcK k;
+    if (bcs) {
+        st = make_bck(g, bcs, k);
+        if (st) return st;
+    }
+    st = bind_speeds(c.sk);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[kProfileMax + 1];
+    hipError_t e = hipSuccess;
+    int made = 0;
+    while (made <= kProfileMax) {
+        e = hipEventCreate(&ev[made]);
+        if (e != hipSuccess) break;
+        ++made;
+    }
+    Probe probe{ev, kernel_kind, 0, kProfileMax, hipSuccess};
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess)
+        e = run_rk3(c, met, q, work, dt, s, bcs ? &k : nullptr, t, sch->mu > 0.0 ? vwork : nullptr, true,
+                    nullptr, &probe);
+    if (e == hipSuccess) e = probe.err;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess && probe.n > 0) e = hipEventSynchronize(ev[probe.n]);
+    for (int i = 0; i < probe.n && e == hipSuccess; ++i) e = hipEventElapsedTime(&kernel_ms[i], ev[i], ev[i + 1]);
+    for (int i = 0; i < made; ++i) hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return hip_fail(e, "fp_profile_step");
+    *n_kernels = probe.n;
     return FP_OK;
 }
 

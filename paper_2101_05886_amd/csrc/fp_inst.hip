@@ -78,13 +78,20 @@ void launch_x(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
 
 template <int DIM, int Y>
 hipError_t run_stage(const SweepArgs& a, hipStream_t s) {
-    if (a.glf) launch_glf<DIM, Y>(a, s);
+    if (a.glf) {
+        launch_glf<DIM, Y>(a, s);
+        probe_mark(a.probe, PK_GLF, s);
+    }
     launch_x<DIM, Y>(a, a.ep_first, s);
+    probe_mark(a.probe, PK_XI, s);
     if constexpr (DIM == 3) {
         launch_wg<3, 1, Y>(a, a.ep_mid, s);
+        probe_mark(a.probe, PK_ETA, s);
         launch_wg<3, 2, Y>(a, a.ep_last, s);
+        probe_mark(a.probe, PK_ZETA, s);
     } else {
         launch_wg<2, 1, Y>(a, a.ep_last, s);
+        probe_mark(a.probe, PK_ETA, s);
     }
     return hipGetLastError();
 }

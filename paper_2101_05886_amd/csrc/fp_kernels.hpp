@@ -883,6 +883,30 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_face_flux(GeoK G, SchemeK
 // launch helpers (defined in the instantiation units)
 // ---------------------------------------------------------------------------
 
+// Launch timing of an instrumented step: after each launch the host records
+// an event on the stream and the launch's kind (kinds as fp_profile_step
+// reports them).  The first error stops the recording.
+enum {
+    PK_XI = 0, PK_ETA = 1, PK_ZETA = 2, PK_GHOST = 3, PK_GLF = 5, PK_BC = 6, PK_VFLUX = 7, PK_VDIV = 8,
+    PK_GLF_RESET = 9
+};
+struct Probe {
+    hipEvent_t* ev;  // ev[0] is recorded before the first launch; ev[i + 1] after launch i
+    int32_t* kind;
+    int n, cap;
+    hipError_t err;
+};
+inline void probe_mark(Probe* p, int kind, hipStream_t s) {
+    if (!p || p->err != hipSuccess) return;
+    if (p->n >= p->cap) {
+        p->err = hipErrorInvalidValue;
+        return;
+    }
+    p->err = hipGetLastError();
+    if (p->err == hipSuccess) p->err = hipEventRecord(p->ev[p->n + 1], s);
+    if (p->err == hipSuccess) p->kind[p->n++] = kind;
+}
+
 struct SweepArgs {
     GeoK G;
     SchemeK sk;
@@ -893,6 +917,7 @@ struct SweepArgs {
     int nseg[3];
     int glf;  // 1: reduce the global LF speeds of the stage input into sk.glf first
     double* glf_next;  // the speed set the reduction zeroes for the next stage (or NULL)
+    Probe* probe;      // instrumented step (or NULL)
 };
 
 // one full residual evaluation (all sweeps) of the given instantiation

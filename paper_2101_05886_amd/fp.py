@@ -26,7 +26,8 @@ EXPORTS = ["fp_state_bytes", "fp_metric_bytes", "fp_coord_bytes", "fp_work_bytes
            "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve", "fp_max_dt",
            "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step", "fp_batch_solve",
            "fp_batch_set_links", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error",
-           "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_work_bytes", "fp_viscous_residual", "fp_solve_ns"]
+           "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_work_bytes", "fp_viscous_residual", "fp_solve_ns",
+           "fp_profile_step"]
 
 
 class FPError(RuntimeError):
@@ -90,6 +91,9 @@ def lib():
         L.fp_solve_ns.argtypes = [gp, sp, dp, dp, dp, dp, C.c_double, C.c_int64, vp]
         L.fp_solve_bcs.argtypes = [gp, sp, C.POINTER(FPBcs), dp, dp, dp, C.c_double, C.c_double, C.c_int64, vp]
         L.fp_check_state.argtypes = [gp, sp, dp, dp, vp]
+        L.fp_profile_step.argtypes = [gp, sp, C.POINTER(FPBcs), dp, dp, dp, dp, C.c_double, C.c_double,
+                                      C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32,
+                                      C.POINTER(C.c_int32), vp]
         bp = C.c_void_p
         L.fp_batch_create.argtypes = [sp, C.c_int32, C.POINTER(C.c_void_p)]
         L.fp_batch_set.argtypes = [bp, C.POINTER(FPBlock), C.c_int32, vp]
@@ -107,7 +111,7 @@ def lib():
         for name in ("fp_metrics", "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve",
                      "fp_max_dt", "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step",
                      "fp_batch_solve", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_set_links",
-                     "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_residual", "fp_solve_ns"):
+                     "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_residual", "fp_solve_ns", "fp_profile_step"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -372,6 +376,27 @@ def solve_bcs(grid: Grid, scheme: Scheme, bcs: Bcs, met, q, work, t0: float, dt:
                               _dev(q, state_bytes(grid), "q"), _dev(work, work_bytes(grid), "work"),
                               float(t0), float(dt), int(nsteps), _stream()))
     return q
+
+
+# launch kinds of profile_step
+PROFILE_KINDS = {0: "xi sweep", 1: "eta sweep", 2: "zeta sweep", 3: "frozen ghosts", 5: "GLF speeds",
+                 6: "boundary faces", 7: "viscous fluxes", 8: "viscous divergence", 9: "speed-set reset"}
+
+
+def profile_step(grid: Grid, scheme: Scheme, met, q, work, dt: float, bcs: "Bcs | None" = None, t: float = 0.0,
+                 vwork=None):
+    """One RK3 step of q with per-launch HIP-event timing (fp_profile_step):
+    [(kind, ms)] in launch order (kinds: PROFILE_KINDS)."""
+    g, s = grid.c(), scheme.c()
+    b = C.byref(bcs.c(grid)) if bcs is not None else None
+    vw = _dev(vwork, viscous_work_bytes(grid), "vwork") if vwork is not None else None
+    ms = (C.c_float * 32)()
+    kinds = (C.c_int32 * 32)()
+    n = C.c_int32(0)
+    _check(lib().fp_profile_step(C.byref(g), C.byref(s), b, _dev(met, metric_bytes(grid), "met"),
+                                 _dev(q, state_bytes(grid), "q"), _dev(work, work_bytes(grid), "work"), vw,
+                                 float(t), float(dt), ms, kinds, 32, C.byref(n), _stream()))
+    return [(int(kinds[i]), float(ms[i])) for i in range(n.value)]
 
 
 def max_dt(grid: Grid, scheme: Scheme, met, q, cfl: float, out=None) -> torch.Tensor:
