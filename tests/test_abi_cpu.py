@@ -71,6 +71,17 @@ def test_null_arrays_rejected():
     assert L.fp_residual(C.byref(g), C.byref(s), None, None, None, None) == fp.FP_EINVAL
     assert L.fp_rk3_step(C.byref(g), C.byref(s), None, None, None, 0.1, None) == fp.FP_EINVAL
     assert L.fp_metrics(C.byref(g), 6, None, None, None) == fp.FP_EINVAL
+    ms, kinds, n = (C.c_float * 32)(), (C.c_int32 * 32)(), C.c_int32(0)
+    assert L.fp_profile_step(C.byref(g), C.byref(s), None, None, None, None, None, 0.0, 0.1, ms, kinds, 32,
+                             C.byref(n), None) == fp.FP_EINVAL
+    # checked before anything touches a device: too small an output, a bad dt
+    buf = (C.c_double * 8)()
+    p = C.cast(buf, C.c_void_p)
+    assert L.fp_profile_step(C.byref(g), C.byref(s), None, p, p, p, None, 0.0, 0.1, ms, kinds, 31,
+                             C.byref(n), None) == fp.FP_EINVAL
+    assert L.fp_profile_step(C.byref(g), C.byref(s), None, p, p, p, None, 0.0, -0.1, ms, kinds, 32,
+                             C.byref(n), None) == fp.FP_EINVAL
+    assert n.value == 0
 
 
 def test_batch_arguments_rejected_without_a_device():
