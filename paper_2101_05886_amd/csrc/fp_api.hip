@@ -253,19 +253,21 @@ EpiK epi(int mode, double* R) {
 // the node fluxes of `qs` (written to vwork); the sweeps then accumulate
 void launch_viscous(const Ctx& c, const double* met, const double* qs, double* vwork, double* R,
                     hipStream_t s, Probe* probe = nullptr) {
-    const dim3 grid((unsigned)visc_blocks(c.G.n));
     const double gam = c.sch.gamma, mu = c.sch.mu;
     const double kappa = mu * gam / ((gam - 1.0) * c.sch.prandtl);
-    if (c.grid.ndim == 3)
-        hipLaunchKernelGGL(k_visc_flux<3>, grid, dim3(256), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
-    else
+    if (c.grid.ndim == 3) {
+        const dim3 grid((unsigned)visc_march_blocks(c.G.n));
+        hipLaunchKernelGGL(k_visc_flux3, grid, dim3(512), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
+        probe_mark(probe, PK_VFLUX, s);
+        hipLaunchKernelGGL(k_visc_div3, grid, dim3(512), 0, s, c.G, (const double*)vwork, R);
+        probe_mark(probe, PK_VDIV, s);
+    } else {
+        const dim3 grid((unsigned)visc_blocks(c.G.n));
         hipLaunchKernelGGL(k_visc_flux<2>, grid, dim3(256), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
-    probe_mark(probe, PK_VFLUX, s);
-    if (c.grid.ndim == 3)
-        hipLaunchKernelGGL(k_visc_div<3>, grid, dim3(256), 0, s, c.G, (const double*)vwork, R);
-    else
+        probe_mark(probe, PK_VFLUX, s);
         hipLaunchKernelGGL(k_visc_div<2>, grid, dim3(256), 0, s, c.G, (const double*)vwork, R);
-    probe_mark(probe, PK_VDIV, s);
+        probe_mark(probe, PK_VDIV, s);
+    }
 }
 
 // one residual evaluation; the last sweep applies `last`; with a viscous

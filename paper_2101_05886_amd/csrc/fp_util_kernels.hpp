@@ -441,21 +441,20 @@ __device__ __forceinline__ void visc_prim(const double* __restrict__ q, long vol
     w[DIM] = gm1 * (q[(DIM + 1) * vol + o] - 0.5 * k2) * ir;
 }
 
-// Contravariant viscous fluxes of every direction at every interior node:
-// gradients by the chain rule dphi/dx_j = (1/V) sum_d s_{d,j} D6_d(phi),
-// tau_ij = mu (du_i/dx_j + du_j/dx_i - 2/3 delta_ij div u), the physical
-// fluxes (tau_1j .. tau_nj, u_i tau_ij + kappa dT/dx_j) and
-// Fv~_d = sum_j s_{d,j} Fv_j.  fv: [DIM directions][DIM + 1 components]
-// arrays in the state layout (the mass component, zero, is not stored).
+// The contravariant viscous fluxes at node o from the sixth-order
+// differences dphi[d][a] = D6_d(phi_a) of the primitives phi = (u, T) along
+// every direction and the node's own primitives w: gradients by the chain
+// rule dphi/dx_j = (1/V) sum_d s_{d,j} D6_d(phi), tau_ij = mu (du_i/dx_j +
+// du_j/dx_i - 2/3 delta_ij div u), the physical fluxes (tau_1j .. tau_nj,
+// u_i tau_ij + kappa dT/dx_j) and Fv~_d = sum_j s_{d,j} Fv_j.  fv: [DIM
+// directions][DIM + 1 components] arrays in the state layout (the mass
+// component, zero, is not stored).
 template <int DIM>
-__global__ __launch_bounds__(256) void k_visc_flux(GeoK G, double gamma, double mu, double kappa,
-                                                    const double* __restrict__ met,
-                                                    const double* __restrict__ q, double* __restrict__ fv) {
+__device__ __forceinline__ void visc_node_fluxes(const GeoK& G, double mu, double kappa,
+                                                 const double* __restrict__ met, long o,
+                                                 const double (&dphi)[DIM][DIM + 1], const double (&w)[DIM + 1],
+                                                 double* __restrict__ fv) {
     constexpr int NP = DIM + 1, NMET = DIM == 3 ? 10 : 5;
-    int idx[3];
-    if (!visc_node(G, idx)) return;
-    const long o = G.base + idx[0] + idx[1] * G.sd[1] + (long)idx[2] * G.sd[2];
-    const double gm1 = gamma - 1.0;
     const double iV = 1.0 / met[(NMET - 1) * G.vol + o];
     double grad[NP][DIM];
 #pragma unroll
@@ -463,27 +462,13 @@ __global__ __launch_bounds__(256) void k_visc_flux(GeoK G, double gamma, double 
 #pragma unroll
         for (int j = 0; j < DIM; ++j) grad[a][j] = 0.0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        double dphi[NP];
-#pragma unroll
-        for (int a = 0; a < NP; ++a) dphi[a] = 0.0;
-#pragma unroll
-        for (int s = 1; s <= 3; ++s) {
-            double wp[NP], wm[NP];
-            visc_prim<DIM>(q, G.vol, wrap_node(G, o, idx[d], d, s), gm1, wp);
-            visc_prim<DIM>(q, G.vol, wrap_node(G, o, idx[d], d, -s), gm1, wm);
-#pragma unroll
-            for (int a = 0; a < NP; ++a) dphi[a] += d6w(s) * (wp[a] - wm[a]);
-        }
+    for (int d = 0; d < DIM; ++d)
 #pragma unroll
         for (int j = 0; j < DIM; ++j) {
             const double sdj = met[(d * DIM + j) * G.vol + o] * iV;
 #pragma unroll
-            for (int a = 0; a < NP; ++a) grad[a][j] += sdj * dphi[a];
+            for (int a = 0; a < NP; ++a) grad[a][j] += sdj * dphi[d][a];
         }
-    }
-    double w[NP];
-    visc_prim<DIM>(q, G.vol, o, gm1, w);
     double div = 0.0;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) div += grad[c][c];
@@ -510,9 +495,39 @@ __global__ __launch_bounds__(256) void k_visc_flux(GeoK G, double gamma, double 
         }
 }
 
-// R = sum_d D6_d(Fv~_d) at every interior node (the mass component 0): the
-// viscous part of the residual accumulator, before the inviscid sweeps
-// subtract their flux differences.
+// The viscous node fluxes of a 2D block, one lane per node: the primitives
+// of the stencil neighbours are gathered along each direction.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_visc_flux(GeoK G, double gamma, double mu, double kappa,
+                                                    const double* __restrict__ met,
+                                                    const double* __restrict__ q, double* __restrict__ fv) {
+    constexpr int NP = DIM + 1;
+    int idx[3];
+    if (!visc_node(G, idx)) return;
+    const long o = G.base + idx[0] + idx[1] * G.sd[1] + (long)idx[2] * G.sd[2];
+    const double gm1 = gamma - 1.0;
+    double dphi[DIM][NP];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+        for (int a = 0; a < NP; ++a) dphi[d][a] = 0.0;
+#pragma unroll
+        for (int s = 1; s <= 3; ++s) {
+            double wp[NP], wm[NP];
+            visc_prim<DIM>(q, G.vol, wrap_node(G, o, idx[d], d, s), gm1, wp);
+            visc_prim<DIM>(q, G.vol, wrap_node(G, o, idx[d], d, -s), gm1, wm);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) dphi[d][a] += d6w(s) * (wp[a] - wm[a]);
+        }
+    }
+    double w[NP];
+    visc_prim<DIM>(q, G.vol, o, gm1, w);
+    visc_node_fluxes<DIM>(G, mu, kappa, met, o, dphi, w, fv);
+}
+
+// R = sum_d D6_d(Fv~_d) at every interior node of a 2D block (the mass
+// component 0), one lane per node: the viscous part of the residual
+// accumulator, before the inviscid sweeps subtract their flux differences.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_visc_div(GeoK G, const double* __restrict__ fv, double* __restrict__ R) {
     constexpr int NP = DIM + 1;
@@ -534,6 +549,141 @@ __global__ __launch_bounds__(256) void k_visc_div(GeoK G, const double* __restri
     R[o] = 0.0;
 #pragma unroll
     for (int v = 0; v < NP; ++v) R[(1 + v) * G.vol + o] = acc[v];
+}
+
+// 3D blocks: a workgroup of 512 owns a 64 (i) x 8 (j) tile of columns and a
+// run of kVmK planes, and marches along k.  Each lane keeps the seven planes
+// k-3 .. k+3 of its own column in registers (the zeta differences) and per
+// plane the tile with a halo of three nodes in i and j is staged in LDS (the
+// xi and eta differences): per node about 15 loads of q instead of 95, and
+// every plane is read once per tile.  All axes are periodic, so every index
+// wraps; lanes past the grid's edge load wrapped nodes and store nothing.
+constexpr int kVmI = 64, kVmJ = 8, kVmK = 32, kVmHI = kVmI + 6, kVmHJ = kVmJ + 6;
+inline long visc_march_blocks(const int n[3]) {
+    return (long)((n[0] + kVmI - 1) / kVmI) * ((n[1] + kVmJ - 1) / kVmJ) * ((n[2] + kVmK - 1) / kVmK);
+}
+struct VmTile {
+    int i0, j0, k0, k1;  // tile origin, planes [k0, k1)
+    int i, j;            // this lane's column (wrapped into the grid)
+    bool mine;           // the column is a node of the grid
+};
+__device__ __forceinline__ int wrapi(int t, int n) { return t < 0 ? t + n : (t >= n ? t - n : t); }
+__device__ __forceinline__ VmTile vm_tile(const GeoK& G) {
+    const unsigned L = (unsigned)xcd_block(blockIdx.x, gridDim.x);
+    const unsigned nit = ((unsigned)G.n[0] + kVmI - 1) / kVmI, njt = ((unsigned)G.n[1] + kVmJ - 1) / kVmJ;
+    VmTile t;
+    t.i0 = (int)(L % nit) * kVmI;
+    t.j0 = (int)((L / nit) % njt) * kVmJ;
+    t.k0 = (int)(L / (nit * njt)) * kVmK;
+    t.k1 = min(t.k0 + kVmK, G.n[2]);
+    const int i = t.i0 + (int)(threadIdx.x % kVmI), j = t.j0 + (int)(threadIdx.x / kVmI);
+    t.mine = i < G.n[0] && j < G.n[1];
+    t.i = i % G.n[0];
+    t.j = j % G.n[1];
+    return t;
+}
+__device__ __forceinline__ long vm_off(const GeoK& G, int i, int j, int k) {
+    return G.base + i + (long)j * G.sd[1] + (long)k * G.sd[2];
+}
+
+__global__ __launch_bounds__(512) void k_visc_flux3(GeoK G, double gamma, double mu, double kappa,
+                                                     const double* __restrict__ met,
+                                                     const double* __restrict__ q, double* __restrict__ fv) {
+    __shared__ double L[4][kVmHJ][kVmHI];  // primitives of plane k, tile and halo
+    const VmTile t = vm_tile(G);
+    const double gm1 = gamma - 1.0;
+    const int li = (int)(threadIdx.x % kVmI) + 3, lj = (int)(threadIdx.x / kVmI) + 3;
+    double P[7][4];  // this column's primitives at planes k-3 .. k+3
+#pragma unroll
+    for (int r = 0; r < 6; ++r) visc_prim<3>(q, G.vol, vm_off(G, t.i, t.j, wrapi(t.k0 - 3 + r, G.n[2])), gm1, P[r]);
+    for (int k = t.k0; k < t.k1; ++k) {
+        visc_prim<3>(q, G.vol, vm_off(G, t.i, t.j, wrapi(k + 3, G.n[2])), gm1, P[6]);
+        __syncthreads();  // the previous plane's reads are done
+        for (int e = threadIdx.x; e < kVmHI * kVmHJ; e += blockDim.x) {
+            const int hi = e % kVmHI, hj = e / kVmHI;
+            double w[4];
+            visc_prim<3>(q, G.vol,
+                         vm_off(G, (t.i0 - 3 + hi + 2 * G.n[0]) % G.n[0], (t.j0 - 3 + hj + 2 * G.n[1]) % G.n[1], k),
+                         gm1, w);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) L[a][hj][hi] = w[a];
+        }
+        __syncthreads();
+        double dphi[3][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            dphi[0][a] = 0.0;
+            dphi[1][a] = 0.0;
+            dphi[2][a] = 0.0;
+#pragma unroll
+            for (int s = 1; s <= 3; ++s) {
+                dphi[0][a] += d6w(s) * (L[a][lj][li + s] - L[a][lj][li - s]);
+                dphi[1][a] += d6w(s) * (L[a][lj + s][li] - L[a][lj - s][li]);
+                dphi[2][a] += d6w(s) * (P[3 + s][a] - P[3 - s][a]);
+            }
+        }
+        if (t.mine) visc_node_fluxes<3>(G, mu, kappa, met, vm_off(G, t.i, t.j, k), dphi, P[3], fv);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) P[r][a] = P[r + 1][a];
+    }
+}
+
+__global__ __launch_bounds__(512) void k_visc_div3(GeoK G, const double* __restrict__ fv, double* __restrict__ R) {
+    __shared__ double Lx[4][kVmJ][kVmHI];  // Fv~_xi of plane k: tile rows, halo in i
+    __shared__ double Ly[4][kVmHJ][kVmI];  // Fv~_eta of plane k: tile columns, halo in j
+    const VmTile t = vm_tile(G);
+    const int ti = (int)(threadIdx.x % kVmI), tj = (int)(threadIdx.x / kVmI);
+    double Z[7][4];  // this column's Fv~_zeta at planes k-3 .. k+3
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        const long off = vm_off(G, t.i, t.j, wrapi(t.k0 - 3 + r, G.n[2]));
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Z[r][v] = fv[(8 + v) * G.vol + off];
+    }
+    for (int k = t.k0; k < t.k1; ++k) {
+        {
+            const long off = vm_off(G, t.i, t.j, wrapi(k + 3, G.n[2]));
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Z[6][v] = fv[(8 + v) * G.vol + off];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kVmHI * kVmJ; e += blockDim.x) {
+            const int hi = e % kVmHI, hj = e / kVmHI;
+            const long off = vm_off(G, (t.i0 - 3 + hi + 2 * G.n[0]) % G.n[0], (t.j0 + hj) % G.n[1], k);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Lx[v][hj][hi] = fv[v * G.vol + off];
+        }
+        for (int e = threadIdx.x; e < kVmI * kVmHJ; e += blockDim.x) {
+            const int hi = e % kVmI, hj = e / kVmI;
+            const long off = vm_off(G, (t.i0 + hi) % G.n[0], (t.j0 - 3 + hj + 2 * G.n[1]) % G.n[1], k);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ly[v][hj][hi] = fv[(4 + v) * G.vol + off];
+        }
+        __syncthreads();
+        double acc[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            acc[v] = 0.0;
+#pragma unroll
+            for (int s = 1; s <= 3; ++s) acc[v] += d6w(s) * (Lx[v][tj][ti + 3 + s] - Lx[v][tj][ti + 3 - s]);
+#pragma unroll
+            for (int s = 1; s <= 3; ++s) acc[v] += d6w(s) * (Ly[v][tj + 3 + s][ti] - Ly[v][tj + 3 - s][ti]);
+#pragma unroll
+            for (int s = 1; s <= 3; ++s) acc[v] += d6w(s) * (Z[3 + s][v] - Z[3 - s][v]);
+        }
+        if (t.mine) {
+            const long o = vm_off(G, t.i, t.j, k);
+            R[o] = 0.0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) R[(1 + v) * G.vol + o] = acc[v];
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Z[r][v] = Z[r + 1][v];
+    }
 }
 
 // ---------------------------------------------------------------------------
