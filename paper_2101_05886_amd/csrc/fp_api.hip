@@ -257,9 +257,9 @@ void launch_viscous(const Ctx& c, const double* met, const double* qs, double* v
     const double kappa = mu * gam / ((gam - 1.0) * c.sch.prandtl);
     if (c.grid.ndim == 3) {
         const dim3 grid((unsigned)visc_march_blocks(c.G.n));
-        hipLaunchKernelGGL(k_visc_flux3, grid, dim3(512), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
+        hipLaunchKernelGGL(k_visc_flux3, grid, dim3(kVmI * kVmJ), 0, s, c.G, gam, mu, kappa, met, qs, vwork);
         probe_mark(probe, PK_VFLUX, s);
-        hipLaunchKernelGGL(k_visc_div3, grid, dim3(512), 0, s, c.G, (const double*)vwork, R);
+        hipLaunchKernelGGL(k_visc_div3, grid, dim3(kVmI * kVmJ), 0, s, c.G, (const double*)vwork, R);
         probe_mark(probe, PK_VDIV, s);
     } else {
         const dim3 grid((unsigned)visc_blocks(c.G.n));

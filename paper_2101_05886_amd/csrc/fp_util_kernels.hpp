@@ -551,8 +551,8 @@ __global__ __launch_bounds__(256) void k_visc_div(GeoK G, const double* __restri
     for (int v = 0; v < NP; ++v) R[(1 + v) * G.vol + o] = acc[v];
 }
 
-// 3D blocks: a workgroup of 512 owns a 64 (i) x 8 (j) tile of columns and a
-// run of kVmK planes, and marches along k.  Each lane keeps the seven planes
+// 3D blocks: a workgroup (one lane per column) owns a kVmI (i) x kVmJ (j)
+// tile of columns and a run of kVmK planes, and marches along k.  Each lane keeps the seven planes
 // k-3 .. k+3 of its own column in registers (the zeta differences) and per
 // plane the tile with a halo of three nodes in i and j is staged in LDS (the
 // xi and eta differences): per node about 15 loads of q instead of 95, and
@@ -586,7 +586,7 @@ __device__ __forceinline__ long vm_off(const GeoK& G, int i, int j, int k) {
     return G.base + i + (long)j * G.sd[1] + (long)k * G.sd[2];
 }
 
-__global__ __launch_bounds__(512) void k_visc_flux3(GeoK G, double gamma, double mu, double kappa,
+__global__ __launch_bounds__(kVmI * kVmJ) void k_visc_flux3(GeoK G, double gamma, double mu, double kappa,
                                                      const double* __restrict__ met,
                                                      const double* __restrict__ q, double* __restrict__ fv) {
     __shared__ double L[4][kVmHJ][kVmHI];  // primitives of plane k, tile and halo
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(512) void k_visc_flux3(GeoK G, double gamma, double
     }
 }
 
-__global__ __launch_bounds__(512) void k_visc_div3(GeoK G, const double* __restrict__ fv, double* __restrict__ R) {
+__global__ __launch_bounds__(kVmI * kVmJ) void k_visc_div3(GeoK G, const double* __restrict__ fv, double* __restrict__ R) {
     __shared__ double Lx[4][kVmJ][kVmHI];  // Fv~_xi of plane k: tile rows, halo in i
     __shared__ double Ly[4][kVmHJ][kVmI];  // Fv~_eta of plane k: tile columns, halo in j
     const VmTile t = vm_tile(G);
