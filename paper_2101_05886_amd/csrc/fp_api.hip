@@ -1175,7 +1175,7 @@ fp_status fp_batch_create(const fp_scheme* sch, int32_t max_blocks, fp_batch** o
             const int per_cu = occ(k);
             b->grid[p][k] = (per_cu > 0 ? per_cu : 1) * cus;
         }
-        b->grid[p][BK_GHOST] = 4 * cus;
+        b->grid[p][BK_GHOST] = 16 * cus;  // ghost copy and interface exchange: grid-stride, many nodes in flight
     }
     *out = b;
     return FP_OK;

@@ -212,30 +212,48 @@ __global__ __launch_bounds__(256) void kb_frozen_ghosts(const int* __restrict__ 
 // side are copied from the interior layers of block b next to the opposite
 // side.  which = 0, 1, 2: the state registers of RK stage 1 (q), 2 (A),
 // 3 (B); which = 3: the metric arrays.  Node t of all links' ghost slabs
-// (prefix sums lstart) per thread; lanes follow their link forward.
+// (prefix sums lstart) per thread, its link found by binary search.  Within
+// a slab consecutive lanes take nodes consecutive in memory: along the layer
+// for a face of the i axis, along i for the other faces.
 __global__ __launch_bounds__(256) void kb_halo(const int* __restrict__ t_nlink,
                                                const long* __restrict__ t_lstart,
                                                const LinkK* __restrict__ t_links,
                                                const BBlock* __restrict__ t_blk, int ndim, int which) {
     const int nl = *t_nlink;
     const long total = t_lstart[nl];
-    int li = 0;
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-        while (li + 1 < nl && t_lstart[li + 1] <= t) ++li;
+        // the link of node t: the last li with lstart[li] <= t (binary search)
+        int li = 0, hi = nl - 1;
+        while (li < hi) {
+            const int mid = (li + hi + 1) >> 1;
+            if (t_lstart[mid] <= t)
+                li = mid;
+            else
+                hi = mid - 1;
+        }
         const LinkK L = t_links[li];
         const BBlock& A = t_blk[L.a];
         const BBlock& B = t_blk[L.b];
         const int g = A.G.g;
-        long u = t - t_lstart[li];
-        const int l = (int)(u % g);
-        u /= g;
-        long oa = A.G.base, ob = B.G.base;
-        for (int e = 0; e < ndim; ++e) {
-            if (e == L.axis) continue;
-            const long c = u % A.G.n[e];
-            u /= A.G.n[e];
-            oa += c * A.G.sd[e];
-            ob += c * B.G.sd[e];
+        // the transverse axes e1 < e2 (e2 = 2 only in 3D), then the node's
+        // layer l and transverse indices c1, c2
+        const int e1 = L.axis == 0 ? 1 : 0, e2 = L.axis == 2 ? 1 : 2;
+        const long u = t - t_lstart[li];
+        long c1, c2;
+        int l;
+        if (L.axis == 0) {
+            l = (int)(u % g);
+            c1 = (u / g) % A.G.n[e1];
+            c2 = (u / g) / A.G.n[e1];
+        } else {
+            c1 = u % A.G.n[e1];
+            l = (int)((u / A.G.n[e1]) % g);
+            c2 = (u / A.G.n[e1]) / g;
+        }
+        long oa = A.G.base + c1 * A.G.sd[e1], ob = B.G.base + c1 * B.G.sd[e1];
+        if (ndim == 3) {
+            oa += c2 * A.G.sd[e2];
+            ob += c2 * B.G.sd[e2];
         }
         const int ia = L.side ? A.G.n[L.axis] + l : -1 - l;
         const int ib = L.side ? l : B.G.n[L.axis] - 1 - l;
