@@ -652,8 +652,8 @@ def main():
         nv = ndim + 2
         vb = (nv + ndim * ndim + 1 + 2 * ndim * (ndim + 1) + nv) * 8
         vms = per_kind[7] + per_kind[8]
-        viscous = {"kernels": "k_visc_flux + k_visc_div", "ms_per_stage": vms,
-                   "k_visc_flux_ms": per_kind[7], "k_visc_div_ms": per_kind[8], "bytes_per_node": vb,
+        viscous = {"kernels": "k_visc_flux3 + k_visc_div3" if ndim == 3 else "k_visc_flux + k_visc_div",
+                   "ms_per_stage": vms, "fluxes_ms": per_kind[7], "divergence_ms": per_kind[8], "bytes_per_node": vb,
                    "achieved_gbs": vb * nodes_of(w) / (vms * 1e-3) / 1e9, "peak_gbs": PEAK_HBM_GBS}
     ftab, fcur = counter_table(FLOPS_FILE)
     ttab, tcur = counter_table(TRAFFIC_FILE)
