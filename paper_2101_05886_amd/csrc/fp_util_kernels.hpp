@@ -166,18 +166,27 @@ __device__ __forceinline__ void frozen_ghost_node(const GeoK& G, int ndim, int n
             t -= c;
             continue;
         }
-        const int ad = (int)(t % (2 * G.g));
-        long rest = t / (2 * G.g);
-        long off = G.base + (long)(ad < G.g ? ad - G.g : G.n[d] + ad - G.g) * G.sd[d];
-        for (int e = 0; e < ndim; ++e) {
-            if (e == d) continue;
-            off += (rest % G.n[e]) * G.sd[e];
-            rest /= G.n[e];
+        // the layer ad (both sides) and the transverse indices c1 (axis e1),
+        // c2 (axis e2, 3D): consecutive lanes take nodes consecutive in
+        // memory, along the layers for the slabs of the i axis, along i else
+        const int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+        int ad;
+        long c1, c2;
+        if (d == 0) {
+            ad = (int)(t % (2 * G.g));
+            c1 = (t / (2 * G.g)) % G.n[e1];
+            c2 = (t / (2 * G.g)) / G.n[e1];
+        } else {
+            c1 = t % G.n[e1];
+            ad = (int)((t / G.n[e1]) % (2 * G.g));
+            c2 = (t / G.n[e1]) / (2 * G.g);
         }
+        long off = G.base + (long)(ad < G.g ? ad - G.g : G.n[d] + ad - G.g) * G.sd[d] + c1 * G.sd[e1];
+        if (ndim == 3) off += c2 * G.sd[e2];
         for (int v = 0; v < nvar; ++v) {
-            const double x = src[v * G.vol + off];
-            dst1[v * G.vol + off] = x;
-            dst2[v * G.vol + off] = x;
+            const double x = gmem(src)[v * G.vol + off];
+            gmem(dst1)[v * G.vol + off] = x;
+            gmem(dst2)[v * G.vol + off] = x;
         }
         return;
     }
@@ -260,12 +269,12 @@ __global__ __launch_bounds__(256) void kb_halo(const int* __restrict__ t_nlink,
         oa += (long)ia * A.G.sd[L.axis];
         ob += (long)ib * B.G.sd[L.axis];
         if (which == 3) {
-            double* dst = const_cast<double*>(A.met);
+            gdouble* dst = gmem(const_cast<double*>(A.met));
             const int nmet = ndim == 3 ? 10 : 5;
-            for (int v = 0; v < nmet; ++v) dst[v * A.G.vol + oa] = B.met[v * B.G.vol + ob];
+            for (int v = 0; v < nmet; ++v) dst[v * A.G.vol + oa] = gmem(B.met)[v * B.G.vol + ob];
         } else {
-            double* dst = which == 0 ? A.q : (which == 1 ? A.A : A.B);
-            const double* src = which == 0 ? B.q : (which == 1 ? B.A : B.B);
+            gdouble* dst = gmem(which == 0 ? A.q : (which == 1 ? A.A : A.B));
+            const gdouble* src = gmem(which == 0 ? B.q : (which == 1 ? B.A : B.B));
             for (int v = 0; v < ndim + 2; ++v) dst[v * A.G.vol + oa] = src[v * B.G.vol + ob];
         }
     }
