@@ -37,6 +37,9 @@ struct GeoK {
 //             out = u (first stage) or a qn + b u (TVD RK3 stages 2, 3)
 enum { EPI_FIRST = 0, EPI_MID = 1, EPI_LAST_RES = 2, EPI_LAST_RK = 3 };
 
+// The eta / zeta sweeps, which apply the final epilogues, take qin and 1/J
+// from the stencil rows they staged: qin must be the array the sweep reads
+// and metV the metric array's 1/J component.
 struct EpiK {
     int mode;
     int stage0;
@@ -66,16 +69,21 @@ struct EpiPre {
     double R[NV], qin[NV], qn[NV], V;
 };
 
+// (own_qv: the caller supplies 1/J and the stage input itself, from values
+// it has staged already)
 template <int NV>
-__device__ __forceinline__ void epi_load(const EpiK& ep, long vol, long off, EpiPre<NV>& p) {
+__device__ __forceinline__ void epi_load(const EpiK& ep, long vol, long off, EpiPre<NV>& p,
+                                         bool own_qv = false) {
     if (ep.mode == EPI_FIRST) return;
 #pragma unroll
     for (int v = 0; v < NV; ++v) p.R[v] = gmem(ep.R)[v * vol + off];
     if (ep.mode == EPI_MID) return;
-    p.V = gmem(ep.metV)[off];
+    if (!own_qv) p.V = gmem(ep.metV)[off];
     if (ep.mode == EPI_LAST_RES) return;
+    if (!own_qv) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) p.qin[v] = gmem(ep.qin)[v * vol + off];
+        for (int v = 0; v < NV; ++v) p.qin[v] = gmem(ep.qin)[v * vol + off];
+    }
     if (ep.stage0) return;
 #pragma unroll
     for (int v = 0; v < NV; ++v) p.qn[v] = gmem(ep.qn)[v * vol + off];
@@ -497,6 +505,10 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
     const int iters = (k1 - k0 + 1 + 3) / 4;  // faces k0-1/2 .. k1-1/2
     const int tb = k0 - 1 - W::LO;            // node index of ring row 0
     const int tmax = k1 - 1 + W::HI;          // last row any needed face reads
+    // a final epilogue takes node f's stage input and 1/J from its ring row
+    // (the stage input is the array this sweep reads, ep.qin == qs, and 1/J
+    // the metric array's last component, in every caller) instead of memory
+    constexpr bool own_qv = true;
     auto load_row = [&](int t) {
         if (t > tmax) return;
         const int slot = (t - tb) % W::RING;
@@ -521,11 +533,12 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
         if (it + 1 < iters) load_row(tb + W::WIN + 4 * it + w);  // a row of the next iteration
         // this wave's node f: its epilogue operands load while the face is
         // computed (in FP64 WENO the zeta sweep then spills a few registers,
-        // still faster than waiting for the loads after the face)
+        // still faster than waiting for the loads after the face); 1/J and
+        // the stage input of node f are in its ring row already
         const bool mine = lane_ok && f >= k0 && f < k1;
         const long noff = lb + (long)f * G.sd[DIR];
         EpiPre<NV> pre;
-        if (mine) epi_load<NV>(ep, G.vol, noff, pre);
+        if (mine) epi_load<NV>(ep, G.vol, noff, pre, own_qv);
         double F[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = 0.0;
@@ -544,6 +557,14 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
             double d[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) d[v] = F[v] - prev[v * 64 + lane];
+            if (own_qv && ep.mode >= EPI_LAST_RES) {
+                // node f's ring row (not overwritten before the next
+                // iteration's barrier: the prefetched rows take other slots)
+                const int slot = (f - tb) % W::RING;
+                pre.V = L.ring[slot][NV][lane];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) pre.qin[v] = L.ring[slot][v][lane];
+            }
             epi_store<NV>(ep, G.vol, noff, pre, d);
         }
         __builtin_amdgcn_s_waitcnt(0);  // this wave's row DMA has landed
