@@ -45,7 +45,12 @@ def interior(a, g, ndim):
     return a[(slice(None),) + (slice(g, -g),) * ndim]
 
 
-@pytest.mark.parametrize("ndim,n,Y", [(2, (40, 33), 6), (2, (30, 26), 4), (3, (20, 17, 14), 6)])
+@pytest.mark.parametrize("ndim,n,Y", [(2, (40, 33), 6), (2, (30, 26), 4), (3, (20, 17, 14), 6),
+                                      # the smallest 3D block (every axis at 7..9 nodes: the
+                                      # marching kernels' tiles and halos wrap several times)
+                                      (3, (7, 8, 9), 6),
+                                      # more than one tile and k-run along every axis
+                                      (3, (70, 12, 40), 4)])
 def test_viscous_residual_matches_the_oracle(ndim, n, Y):
     case = G.periodic_case(ndim, n, Y, state="noisy", seed=61)
     og, fg = O.Grid(ndim, n, 3), fp.Grid(ndim, n, 3)
