@@ -125,9 +125,9 @@ size_t fp_coord_bytes(const fp_grid *grid, int32_t metric_order);
  * classes u_n - c, u_n, u_n + c, at doubles 48 k + 16 d .. 48 k + 16 d + 2)
  * and zeroes set k + 1 mod 3 for the next stage; each call zeroes set 0
  * first.  fp_solve_bcs keeps its device time at doubles 144 .. 146.
- * The tail needs no initial contents.  When an axis is frozen,
- * each step first copies the frozen ghost layers of q into the two stage
- * registers. */
+ * The tail needs no initial contents.  When an axis is frozen, the frozen
+ * ghost layers of q are copied into the two stage registers before the
+ * first step of each call (no step writes them again). */
 size_t fp_work_bytes(const fp_grid *grid);
 
 /* Symmetric conservative metrics and 1/J of order Y (Sec. 2.1, eqs. JBabc and
