@@ -97,3 +97,27 @@ def test_batch_arguments_rejected_without_a_device():
     assert L.fp_batch_solve(None, 1, None) == fp.FP_EINVAL
     assert L.fp_batch_autotune(None, None, None) == fp.FP_EINVAL
     L.fp_batch_destroy(None)
+
+
+def test_block_size_limit():
+    # a block holds fewer than 2^29 nodes with its ghosts (the kernels use
+    # 32-bit byte offsets into one variable array): 806^3 (812^3 = 5.354e8
+    # with ghost 3) is the largest cube, 807^3 (813^3 = 5.374e8) is rejected
+    ok = fp.Grid(3, (806, 806, 806), 3)
+    assert fp.state_bytes(ok) == 8 * 5 * 812 ** 3
+    assert fp.work_bytes(ok) == 3 * fp.state_bytes(ok) + 2048
+    big = fp.Grid(3, (807, 807, 807), 3)
+    assert fp.state_bytes(big) == 0
+    L = fp.lib()
+    g, sc = big.c(), fp.Scheme().c()
+    p = C.c_void_p(16)  # never dereferenced: the grid check fails first
+    assert L.fp_rk3_step(C.byref(g), C.byref(sc), p, p, p, 0.1, None) == fp.FP_EINVAL
+    assert b"too large" in L.fp_last_error()
+
+
+def test_zero_steps_is_a_no_op_before_any_device_call():
+    L = fp.lib()
+    g, s = fp.Grid(3, (8, 8, 8), 3).c(), fp.Scheme().c()
+    p = C.c_void_p(16)  # never dereferenced: nothing is launched for zero steps
+    assert L.fp_solve(C.byref(g), C.byref(s), p, p, p, 0.1, 0, None) == fp.FP_OK
+    assert L.fp_solve(C.byref(g), C.byref(s), p, p, p, 0.1, -1, None) == fp.FP_EINVAL
