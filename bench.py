@@ -568,6 +568,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="batched workload only: skip the serving stream reported beside it")
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--n", type=int, default=None,
+                    help="single-block workloads only: nodes per axis instead of the workload's own "
+                         "(a size sweep; the workload's configuration is the default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -585,6 +588,11 @@ def main():
     from paper_2101_05886_amd import fp
 
     w = WORKLOADS[args.workload]
+    if args.n is not None:
+        if "n" not in w or "cuts" in w:
+            print("--n applies to the single-block workloads only", file=sys.stderr)
+            sys.exit(2)
+        w = dict(w, n=args.n, name=w["name"] + f" (resized to {args.n} nodes per axis)")
     if "blocks" in w:
         bench_batch(args, w)
         return
