@@ -10,10 +10,17 @@
 
 // Occupancy target of the face kernels: two waves per SIMD fits the FP64
 // WENO face (the 6-node x 5-field characteristic values dominate) without
-// spilling.
+// spilling.  The FP32-mixed xi sweeps of the six-point stencils (WENO5,
+// LU5, WENOCU6 with metrics of order up to 6) fit three (at most 168
+// registers) and run at three: their LDS window buffers allow it, the
+// eta/zeta rings (72 KB per workgroup) do not; WENO7 and eighth-order
+// metrics would spill at three.
 #ifndef FP_SWEEP_ATTR
 #define FP_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(2, 2)))
 #endif
+#define FP_XWAVES(PREC, RECON, Y) (((PREC) == 1 && (RECON) != 2 && (Y) != 8) ? 3 : 2)
+#define FP_XSWEEP_ATTR(PREC, RECON, Y) \
+    __attribute__((amdgpu_waves_per_eu(FP_XWAVES(PREC, RECON, Y), FP_XWAVES(PREC, RECON, Y))))
 
 namespace fpk {
 
@@ -223,10 +230,13 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // flat index e = L (n0+8) + x + 4 (line L with four extra nodes on each side,
 // x = -4 .. n0+3): slot r (node f-4+r) of face F is entry e(F) + r with
 // e(F) = L (n0+8) + f.  A window of W faces spans W + 7 (lines touched)
-// entries; W is the largest width (at most 64) that fits XE entries.
+// entries; W is the largest width (at most 64) that fits NE entries.  NE = 88
+// holds W = 64 for lines of 30 nodes and more, and keeps the workgroup's
+// double buffers at 50 KB, so three workgroups (three waves per SIMD) fit a
+// CU's LDS.
 template <int DIM>
 struct XLds {
-    static constexpr int NE = 128;          // staged entries per buffer
+    static constexpr int NE = 88;           // staged entries per buffer
     static constexpr int NS = 2 * DIM + 3;  // q, 1/J, s_xi
     double b[2][NS][NE];                    // double buffer: current item, next item
 };
@@ -296,9 +306,13 @@ __device__ __forceinline__ void x_stage(const GeoK& G, const double* __restrict_
     const int g = G.g;
     const int per = G.bc[0] == 0;
     const unsigned np = (it.count + 31) / 32;
+    constexpr int NE = XLds<DIM>::NE;
 #pragma unroll
-    for (int p = 0; p < XLds<DIM>::NE / 32; ++p) {
+    for (int p = 0; p < (NE + 31) / 32; ++p) {
         if ((unsigned)p >= np) break;
+        // a pass moves 32 entries (two lanes per entry); the last one may be
+        // partial, and its lanes past the buffer's end must write nothing
+        if (NE % 32 != 0 && 32u * p + (lane >> 1) >= (unsigned)NE) continue;
         const unsigned k = it.f0 + 32u * p + (lane >> 1);  // from the start of line L0's entries
         const unsigned dL = small_div(k, inv_ne);
         const int x = (int)(k - dL * ne) - 4;
@@ -387,7 +401,7 @@ __device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, cons
 // Persistent xi sweep of one block: wave w of the grid takes items w,
 // w + (waves of the grid), ..., staging the next item while it computes.
 template <int DIM, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_x(GeoK G, SchemeK sk,
+__global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void k_sweep_x(GeoK G, SchemeK sk,
                                                                const double* __restrict__ met,
                                                                const double* qs, EpiK ep) {
     __shared__ XLds<DIM> lds[4];
@@ -825,7 +839,7 @@ __device__ __forceinline__ EpiK stage_epi(const BBlock& b, int stage, int mode, 
 // batch's wave items w, w + (waves of the grid), ..., staging the next item
 // (possibly of another block) while it computes.
 template <int DIM, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_x(const int* __restrict__ t_nblk,
+__global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void kb_sweep_x(const int* __restrict__ t_nblk,
                                                                 const long* __restrict__ t_start,
                                                                 const BBlock* __restrict__ t_blk, int cap,
                                                                 SchemeK sk, int stage) {
