@@ -526,7 +526,7 @@ void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, const 
             bool frozen = false;
             for (int d = 0; d < ndim; ++d) frozen = frozen || fb.grid.bc[d] == FP_BC_FROZEN;
             long items[BK_KINDS];
-            items[BK_X] = sweep_x_items(B.G.n);
+            items[BK_X] = sweep_x_items(B.G.n, x_entries(b->sch.precision, b->sch.recon, b->sch.metric_order));
             items[BK_ETA] = sweep_wg_items(B.G.n, 1, B.S[1]);
             items[BK_ZETA] = ndim == 3 ? sweep_wg_items(B.G.n, 2, B.S[2]) : 0;
             items[BK_GHOST] = frozen ? (frozen_slab_nodes(B.G, ndim) + 255) / 256 : 0;

@@ -70,7 +70,7 @@ int resident(K* kern) {
 template <int DIM, int Y>
 void launch_x(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
     static const int res = resident(&k_sweep_x<DIM, R, Y, P>);
-    const long items = sweep_x_items(a.G.n);
+    const long items = sweep_x_items(a.G.n, x_entries(P, R, Y));
     const long wgs = (items + 3) / 4;
     hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3((unsigned)(wgs < res ? wgs : res)), dim3(256), 0, s,
                        a.G, a.sk, a.met, a.qs, ep);

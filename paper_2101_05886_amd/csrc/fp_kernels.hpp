@@ -230,27 +230,30 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 // flat index e = L (n0+8) + x + 4 (line L with four extra nodes on each side,
 // x = -4 .. n0+3): slot r (node f-4+r) of face F is entry e(F) + r with
 // e(F) = L (n0+8) + f.  A window of W faces spans W + 7 (lines touched)
-// entries; W is the largest width (at most 64) that fits NE entries.  NE = 88
-// holds W = 64 for lines of 30 nodes and more, and keeps the workgroup's
-// double buffers at 50 KB, so three workgroups (three waves per SIMD) fit a
-// CU's LDS.
-template <int DIM>
+// entries; W is the largest width (at most 64) that fits NE entries.  The
+// sweeps that run three waves per SIMD stage NE = 88 entries (W = 64 still
+// for lines of 30 nodes and more): the workgroup's double buffers then take
+// 50 KB and three workgroups fit a CU's LDS; the others stage 128.
+template <int DIM, int NE_>
 struct XLds {
-    static constexpr int NE = 88;           // staged entries per buffer
+    static constexpr int NE = NE_;          // staged entries per buffer
     static constexpr int NS = 2 * DIM + 3;  // q, 1/J, s_xi
     double b[2][NS][NE];                    // double buffer: current item, next item
 };
+__device__ __host__ constexpr int x_entries(int prec, int recon, int Y) {
+    return FP_XWAVES(prec, recon, Y) == 3 ? 88 : 128;
+}
 
-__device__ __host__ __forceinline__ int x_window(int n0) {
+__device__ __host__ __forceinline__ int x_window(int n0, int ne) {
     int W = 64;
-    while (W > 2 && W + 7 * ((W + n0) / (n0 + 1) + 1) > XLds<3>::NE) --W;
+    while (W > 2 && W + 7 * ((W + n0) / (n0 + 1) + 1) > ne) --W;
     return W;
 }
 
-// wave items of the xi sweep of one block
-__device__ __host__ __forceinline__ long sweep_x_items(const int n[3]) {
+// wave items of the xi sweep of one block (ne: the sweep's staged entries)
+__device__ __host__ __forceinline__ long sweep_x_items(const int n[3], int ne) {
     const long total = (long)(n[0] + 1) * n[1] * n[2];
-    const int W = x_window(n[0]);
+    const int W = x_window(n[0], ne);
     return (total - 1 + W - 2) / (W - 1);
 }
 
@@ -294,9 +297,9 @@ __device__ __forceinline__ XItem x_item(const GeoK& G, long j, int W) {
 }
 
 // Stage item j's stencil entries into buf (all 64 lanes; asynchronous).
-template <int DIM>
+template <int DIM, int NE>
 __device__ __forceinline__ void x_stage(const GeoK& G, const double* __restrict__ met, const double* qs,
-                                        long j, int W, double (*buf)[XLds<DIM>::NE]) {
+                                        long j, int W, double (*buf)[NE]) {
     constexpr int NV = DIM + 2;
     constexpr int NMET = DIM == 3 ? 10 : 5;
     const unsigned lane = threadIdx.x & 63;
@@ -306,7 +309,6 @@ __device__ __forceinline__ void x_stage(const GeoK& G, const double* __restrict_
     const int g = G.g;
     const int per = G.bc[0] == 0;
     const unsigned np = (it.count + 31) / 32;
-    constexpr int NE = XLds<DIM>::NE;
 #pragma unroll
     for (int p = 0; p < (NE + 31) / 32; ++p) {
         if ((unsigned)p >= np) break;
@@ -340,9 +342,9 @@ __device__ __forceinline__ void x_stage(const GeoK& G, const double* __restrict_
 }
 
 // Stencil reads of one lane's xi face from the wave's staged entries.
-template <int DIM>
+template <int DIM, int NE>
 struct XLoader {
-    const double (*buf)[XLds<DIM>::NE];
+    const double (*buf)[NE];
     unsigned ea;  // byte offset of entry e(F) in a variable row
 
     __device__ __forceinline__ XLoader after(double dep) const {
@@ -353,7 +355,6 @@ struct XLoader {
 
     __device__ __forceinline__ void slot(int r, double (&qv)[DIM + 2], double& V,
                                          double (&s)[DIM]) const {
-        constexpr int NE = XLds<DIM>::NE;
         const char* row = reinterpret_cast<const char*>(&buf[0][0]) + ea + r * 8;
 #pragma unroll
         for (int v = 0; v < DIM + 2; ++v) qv[v] = *reinterpret_cast<const double*>(row + v * NE * 8);
@@ -367,7 +368,7 @@ struct XLoader {
 // the epilogue (all 64 lanes must call this: the lane shift).
 template <int DIM, int RECON, int Y, int PREC>
 __device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, const EpiK& ep, long j, int W,
-                                          const double (*buf)[XLds<DIM>::NE]) {
+                                          const double (*buf)[x_entries(PREC, RECON, Y)]) {
     constexpr int NV = DIM + 2;
     const unsigned lane = threadIdx.x & 63;
     const unsigned nf = (unsigned)G.n[0] + 1, ne = (unsigned)G.n[0] + 8;
@@ -382,7 +383,7 @@ __device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, cons
     const unsigned dL = small_div(k, 1.0f / (float)nf);
     const unsigned f = k - dL * nf;
     if (active) {
-        XLoader<DIM> ld;
+        XLoader<DIM, x_entries(PREC, RECON, Y)> ld;
         ld.buf = buf;
         ld.ea = (dL * ne + f - it.f0) * 8u;
         face_flux<DIM, RECON, Y, char_t<PREC>>(ld, sk, fl);
@@ -404,18 +405,19 @@ template <int DIM, int RECON, int Y, int PREC>
 __global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void k_sweep_x(GeoK G, SchemeK sk,
                                                                const double* __restrict__ met,
                                                                const double* qs, EpiK ep) {
-    __shared__ XLds<DIM> lds[4];
-    XLds<DIM>& L = lds[wave_id()];
+    constexpr int NE = x_entries(PREC, RECON, Y);
+    __shared__ XLds<DIM, NE> lds[4];
+    XLds<DIM, NE>& L = lds[wave_id()];
     const long nw = (long)gridDim.x * 4;
-    const long items = sweep_x_items(G.n);
-    const int W = x_window(G.n[0]);
+    const long items = sweep_x_items(G.n, NE);
+    const int W = x_window(G.n[0], NE);
     long j = (long)blockIdx.x * 4 + wave_id();
     int cur = 0;
-    if (j < items) x_stage<DIM>(G, met, qs, j, W, L.b[0]);
+    if (j < items) x_stage<DIM, NE>(G, met, qs, j, W, L.b[0]);
     for (; j < items; j += nw, cur ^= 1) {
         __builtin_amdgcn_s_waitcnt(0);  // item j's entries are in LDS
         asm volatile("" ::: "memory");
-        if (j + nw < items) x_stage<DIM>(G, met, qs, j + nw, W, L.b[cur ^ 1]);
+        if (j + nw < items) x_stage<DIM, NE>(G, met, qs, j + nw, W, L.b[cur ^ 1]);
         x_compute<DIM, RECON, Y, PREC>(G, sk, ep, j, W, L.b[cur]);
     }
 }
@@ -843,8 +845,9 @@ __global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void kb_sweep_x
                                                                 const long* __restrict__ t_start,
                                                                 const BBlock* __restrict__ t_blk, int cap,
                                                                 SchemeK sk, int stage) {
-    __shared__ XLds<DIM> lds[4];
-    XLds<DIM>& L = lds[wave_id()];
+    constexpr int NE = x_entries(PREC, RECON, Y);
+    __shared__ XLds<DIM, NE> lds[4];
+    XLds<DIM, NE>& L = lds[wave_id()];
     const int nblk = *t_nblk;
     const long* __restrict__ st = t_start + BK_X * (cap + 1);
     const long total = st[nblk];
@@ -855,7 +858,7 @@ __global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void kb_sweep_x
     if (item < total) {
         b = find_block(st, nblk, item);
         const BBlock& B = t_blk[b];
-        x_stage<DIM>(B.G, B.met, stage_in(B, stage), item - st[b], x_window(B.G.n[0]), L.b[0]);
+        x_stage<DIM, NE>(B.G, B.met, stage_in(B, stage), item - st[b], x_window(B.G.n[0], NE), L.b[0]);
     }
     for (; item < total; item += nw, cur ^= 1) {
         __builtin_amdgcn_s_waitcnt(0);
@@ -864,11 +867,12 @@ __global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void kb_sweep_x
         if (item + nw < total) {
             bn = advance_block(st, nblk, b, item + nw);
             const BBlock& N = t_blk[bn];
-            x_stage<DIM>(N.G, N.met, stage_in(N, stage), item + nw - st[bn], x_window(N.G.n[0]), L.b[cur ^ 1]);
+            x_stage<DIM, NE>(N.G, N.met, stage_in(N, stage), item + nw - st[bn], x_window(N.G.n[0], NE),
+                             L.b[cur ^ 1]);
         }
         const BBlock& B = t_blk[b];
         const EpiK ep = stage_epi(B, stage, EPI_FIRST, DIM);
-        x_compute<DIM, RECON, Y, PREC>(B.G, sk, ep, item - st[b], x_window(B.G.n[0]), L.b[cur]);
+        x_compute<DIM, RECON, Y, PREC>(B.G, sk, ep, item - st[b], x_window(B.G.n[0], NE), L.b[cur]);
         b = bn;
     }
 }
