@@ -67,13 +67,23 @@ int resident(K* kern) {
     return per * cus;
 }
 
-template <int DIM, int Y>
-void launch_x(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
-    static const int res = resident(&k_sweep_x<DIM, R, Y, P>);
+template <int DIM, int Y, bool ACC>
+void launch_x_mode(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
+    static const int res = resident(&k_sweep_x<DIM, R, Y, P, ACC>);
     const long items = sweep_x_items(a.G.n, x_entries(P, R, Y));
     const long wgs = (items + 3) / 4;
-    hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P>), dim3((unsigned)(wgs < res ? wgs : res)), dim3(256), 0, s,
-                       a.G, a.sk, a.met, a.qs, ep);
+    hipLaunchKernelGGL((k_sweep_x<DIM, R, Y, P, ACC>), dim3((unsigned)(wgs < res ? wgs : res)), dim3(256), 0,
+                       s, a.G, a.sk, a.met, a.qs, ep);
+}
+
+// the xi sweep writes the accumulator (FIRST), or adds to it after the
+// viscous part or a caller's accumulation
+template <int DIM, int Y>
+void launch_x(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
+    if (ep.mode == EPI_FIRST)
+        launch_x_mode<DIM, Y, false>(a, ep, s);
+    else
+        launch_x_mode<DIM, Y, true>(a, ep, s);
 }
 
 template <int DIM, int Y>

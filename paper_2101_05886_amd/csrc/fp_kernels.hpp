@@ -96,6 +96,14 @@ __device__ __forceinline__ void epi_load(const EpiK& ep, long vol, long off, Epi
     for (int v = 0; v < NV; ++v) p.qn[v] = gmem(ep.qn)[v * vol + off];
 }
 
+// The same epilogue with its mode fixed to MID (for a sweep that is never
+// the last of a stage), so that no final-epilogue code is compiled in.
+__device__ __forceinline__ EpiK epi_mid(const EpiK& ep) {
+    EpiK e = ep;
+    e.mode = EPI_MID;
+    return e;
+}
+
 template <int NV>
 __device__ __forceinline__ void epi_store(const EpiK& ep, long vol, long off, const EpiPre<NV>& p,
                                           const double (&d)[NV]) {
@@ -129,31 +137,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const double* base, long e
 }
 __device__ __forceinline__ double ldb(const double* base, long elems, unsigned byteoff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(buf(base, elems), byteoff, 0, 0));
-}
-
-template <int NV>
-__device__ __forceinline__ void epilogue(const EpiK& ep, long vol, long off, const double (&d)[NV]) {
-    gdouble* R = gmem(ep.R);
-    if (ep.mode == EPI_FIRST) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) R[v * vol + off] = -d[v];
-    } else if (ep.mode == EPI_MID) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) R[v * vol + off] -= d[v];
-    } else if (ep.mode == EPI_LAST_RES) {
-        const double V = gmem(ep.metV)[off];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) gmem(ep.out)[v * vol + off] = (R[v * vol + off] - d[v]) / V;
-    } else {
-        const double V = gmem(ep.metV)[off];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const long o = v * vol + off;
-            const double k = (R[o] - d[v]) / V;
-            const double u = gmem(ep.qin)[o] + ep.dt * k;
-            gmem(ep.out)[o] = ep.stage0 ? u : ep.a * gmem(ep.qn)[o] + ep.b * u;
-        }
-    }
 }
 
 // Reads the stencil of face i+1/2 of one grid line along axis DIR: slot r
@@ -365,8 +348,11 @@ struct XLoader {
 };
 
 // Faces of item j from its staged entries, the lane-shift difference and
-// the epilogue (all 64 lanes must call this: the lane shift).
-template <int DIM, int RECON, int Y, int PREC>
+// the epilogue (all 64 lanes must call this: the lane shift).  The xi sweep
+// comes first in a stage, so its epilogue is FIRST (ACC = false: R = -d,
+// nothing to load) or MID (ACC = true: R -= d, after the viscous part or a
+// caller's accumulation; R loads while the face is computed).
+template <int DIM, int RECON, int Y, int PREC, bool ACC>
 __device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, const EpiK& ep, long j, int W,
                                           const double (*buf)[x_entries(PREC, RECON, Y)]) {
     constexpr int NV = DIM + 2;
@@ -382,6 +368,16 @@ __device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, cons
     const unsigned k = it.f0 + lane;  // from the first face of line L0
     const unsigned dL = small_div(k, 1.0f / (float)nf);
     const unsigned f = k - dL * nf;
+    // lane l > 0 writes node f - 1, between its face and lane l - 1's
+    const bool writes = active && lane > 0 && f > 0;
+    long noff = 0;
+    EpiPre<NV> pre;
+    if (writes) {
+        unsigned l1, l2;
+        line_step(it.a1, it.a2, dL, (unsigned)G.n[1], l1, l2);
+        noff = G.base + (long)l1 * G.sd[1] + (long)l2 * G.sd[2] + (f - 1);
+        if (ACC) epi_load<NV>(epi_mid(ep), G.vol, noff, pre);
+    }
     if (active) {
         XLoader<DIM, x_entries(PREC, RECON, Y)> ld;
         ld.buf = buf;
@@ -391,20 +387,25 @@ __device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, cons
     double d[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) d[v] = fl[v] - __shfl_up(fl[v], 1, 64);
-    if (active && lane > 0 && f > 0) {
-        unsigned l1, l2;
-        line_step(it.a1, it.a2, dL, (unsigned)G.n[1], l1, l2);
-        const long lb = G.base + (long)l1 * G.sd[1] + (long)l2 * G.sd[2];
-        epilogue<NV>(ep, G.vol, lb + (f - 1), d);
+    if (writes) {
+        if (ACC) {
+            epi_store<NV>(epi_mid(ep), G.vol, noff, pre, d);
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) gmem(ep.R)[v * G.vol + noff] = -d[v];
+        }
     }
 }
 
 // Persistent xi sweep of one block: wave w of the grid takes items w,
-// w + (waves of the grid), ..., staging the next item while it computes.
-template <int DIM, int RECON, int Y, int PREC>
-__global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void k_sweep_x(GeoK G, SchemeK sk,
-                                                               const double* __restrict__ met,
-                                                               const double* qs, EpiK ep) {
+// w + (waves of the grid), ..., staging the next item while it computes
+// (ACC: the epilogue is MID, not FIRST; those kernels run at two waves per
+// SIMD, the accumulator's registers do not fit three).
+#define FP_XWAVES_ACC(PREC, RECON, Y, ACC) ((ACC) ? 2 : FP_XWAVES(PREC, RECON, Y))
+template <int DIM, int RECON, int Y, int PREC, bool ACC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FP_XWAVES_ACC(PREC, RECON, Y, ACC),
+                                                                     FP_XWAVES_ACC(PREC, RECON, Y, ACC))))
+void k_sweep_x(GeoK G, SchemeK sk, const double* __restrict__ met, const double* qs, EpiK ep) {
     constexpr int NE = x_entries(PREC, RECON, Y);
     __shared__ XLds<DIM, NE> lds[4];
     XLds<DIM, NE>& L = lds[wave_id()];
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void k_sweep_x(
         __builtin_amdgcn_s_waitcnt(0);  // item j's entries are in LDS
         asm volatile("" ::: "memory");
         if (j + nw < items) x_stage<DIM, NE>(G, met, qs, j + nw, W, L.b[cur ^ 1]);
-        x_compute<DIM, RECON, Y, PREC>(G, sk, ep, j, W, L.b[cur]);
+        x_compute<DIM, RECON, Y, PREC, ACC>(G, sk, ep, j, W, L.b[cur]);
     }
 }
 
@@ -872,7 +873,7 @@ __global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void kb_sweep_x
         }
         const BBlock& B = t_blk[b];
         const EpiK ep = stage_epi(B, stage, EPI_FIRST, DIM);
-        x_compute<DIM, RECON, Y, PREC>(B.G, sk, ep, item - st[b], x_window(B.G.n[0], NE), L.b[cur]);
+        x_compute<DIM, RECON, Y, PREC, false>(B.G, sk, ep, item - st[b], x_window(B.G.n[0], NE), L.b[cur]);
         b = bn;
     }
 }
