@@ -142,6 +142,32 @@ def test_xi_sweep_short_lines(n, recon, prec):
     assert relerr(interior(res, 3, 3), interior(ref, 3, 3)) <= (1e-11 if prec == "fp64" else 1e-4)
 
 
+# Accumulating direction residuals: with accumulate set, each direction adds
+# its flux difference to what the array holds (the xi sweep then runs its
+# accumulating kernel variant), so the result is the held values plus the
+# direction's own residual, and the ghost layers keep theirs.
+ACC_CASES = [(2, (5, 7)), (2, (40, 33)), (3, (3, 4, 5)), (3, (29, 5, 3)), (3, (24, 20, 18))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("ndim,n", ACC_CASES, ids=[f"{c[0]}d-{'x'.join(map(str, c[1]))}" for c in ACC_CASES])
+def test_residual_dir_accumulates(ndim, n, prec):
+    case = G.periodic_case(ndim, n, 6)
+    og, fg = grids(case)
+    met = O.metrics(og, 6, case["xyz"])
+    fsc = fp.Scheme("weno5", 6, True, precision=prec)
+    mg, qg = dev(met), dev(case["q"])
+    acc0 = np.random.Generator(np.random.PCG64(7)).standard_normal(case["q"].shape)
+    ghost = np.ones(acc0.shape[1:], dtype=bool)
+    ghost[(slice(3, -3),) * ndim] = False
+    for d in range(ndim):
+        own = host(fp.residual_dir(fg, fsc, mg, qg, d, torch.zeros_like(qg)))
+        got = host(fp.residual_dir(fg, fsc, mg, qg, d, dev(acc0), accumulate=True))
+        want = interior(acc0, 3, ndim) + interior(own, 3, ndim)
+        assert np.abs(interior(got, 3, ndim) - want).max() <= 1e-14 * np.abs(want).max(), f"direction {d}"
+        assert np.array_equal(got[:, ghost], acc0[:, ghost]), f"direction {d}"
+
+
 RK_CASES = [(2, (70, 45), 2, "weno5"), (2, (64, 64), 6, "linup5"), (3, (21, 18, 16), 6, "weno5"),
             (3, (20, 20, 20), 2, "linup5")]
 
