@@ -30,12 +30,22 @@ inline SchemeK dir_sk(const SchemeK& sk, int d) {
     return k;
 }
 
-template <int DIM, int DIR, int Y>
-void launch_wg(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
+template <int DIM, int DIR, int Y, int MODE>
+void launch_wg_mode(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
     constexpr int OTH = DIR == 1 ? 2 : 1;
     const long lblocks = ((long)a.G.n[0] * a.G.n[OTH] + 63) / 64;
-    hipLaunchKernelGGL((k_sweep_wg<DIM, DIR, R, Y, P>), dim3((unsigned)(lblocks * a.nseg[DIR])),
+    hipLaunchKernelGGL((k_sweep_wg<DIM, DIR, R, Y, P, MODE>), dim3((unsigned)(lblocks * a.nseg[DIR])),
                        dim3(256), 0, s, a.G, dir_sk(a.sk, DIR), a.met, a.qs, ep, a.S[DIR]);
+}
+
+template <int DIM, int DIR, int Y>
+void launch_wg(const SweepArgs& a, const EpiK& ep, hipStream_t s) {
+    switch (ep.mode) {
+    case EPI_FIRST: launch_wg_mode<DIM, DIR, Y, EPI_FIRST>(a, ep, s); break;
+    case EPI_MID: launch_wg_mode<DIM, DIR, Y, EPI_MID>(a, ep, s); break;
+    case EPI_LAST_RES: launch_wg_mode<DIM, DIR, Y, EPI_LAST_RES>(a, ep, s); break;
+    default: launch_wg_mode<DIM, DIR, Y, EPI_LAST_RK>(a, ep, s); break;
+    }
 }
 
 // global LF speeds of every direction from the stage input (when asked

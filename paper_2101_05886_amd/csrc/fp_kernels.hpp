@@ -602,12 +602,17 @@ inline long sweep_wg_items(const int n[3], int dir, int S) {
     return lblocks * ((n[dir] + S - 1) / S);
 }
 
-template <int DIM, int DIR, int RECON, int Y, int PREC>
+// One launch of the eta / zeta sweep of one block, with its epilogue mode
+// (EPI_*) fixed at compile time, as in the batched sweeps, so that only that
+// epilogue's registers are allocated.
+template <int DIM, int DIR, int RECON, int Y, int PREC, int MODE>
 __global__ __launch_bounds__(256) FP_SWEEP_ATTR void k_sweep_wg(GeoK G, SchemeK sk,
                                                                 const double* __restrict__ met,
                                                                 const double* qs, EpiK ep, int S) {
     __shared__ WgLds<DIM, wide_stencil(RECON, Y)> lds;
-    sweep_wg_item<DIM, DIR, RECON, Y, PREC>(G, sk, met, qs, ep, S, blockIdx.x, lds);
+    EpiK e = ep;
+    e.mode = MODE;
+    sweep_wg_item<DIM, DIR, RECON, Y, PREC>(G, sk, met, qs, e, S, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
