@@ -114,12 +114,14 @@ __device__ __forceinline__ void epi_store(const EpiK& ep, long vol, long off, co
 #pragma unroll
         for (int v = 0; v < NV; ++v) gmem(ep.R)[v * vol + off] = p.R[v] - d[v];
     } else if (ep.mode == EPI_LAST_RES) {
+        const double J = 1.0 / p.V;  // one division per node, not one per variable
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gmem(ep.out)[v * vol + off] = (p.R[v] - d[v]) / p.V;
+        for (int v = 0; v < NV; ++v) gmem(ep.out)[v * vol + off] = (p.R[v] - d[v]) * J;
     } else {
+        const double J = 1.0 / p.V;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double k = (p.R[v] - d[v]) / p.V;
+            const double k = (p.R[v] - d[v]) * J;
             const double u = p.qin[v] + ep.dt * k;
             gmem(ep.out)[v * vol + off] = ep.stage0 ? u : ep.a * p.qn[v] + ep.b * u;
         }
