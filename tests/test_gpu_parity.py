@@ -121,25 +121,27 @@ def test_face_fluxes_and_residual(ndim, n, Y, recon, reform, state):
 # 64 faces.  Every xi difference of the sweep is the difference of the
 # face-flux kernel's fluxes (the same face code, one lane per face), and the
 # residual meets the oracle bar of its precision.
-SHORT_X = [(3, 4, 5), (5, 3, 7), (13, 6, 4), (29, 5, 3), (30, 4, 4), (67, 3, 3)]
+SHORT_X = [(3, 4, 5), (5, 3, 7), (13, 6, 4), (29, 5, 3), (30, 4, 4), (67, 3, 3),
+           (3, 5), (13, 4), (29, 6), (67, 3)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("recon", ["weno5", "linup5", "wenocu6"])
 @pytest.mark.parametrize("n", SHORT_X, ids=["x".join(map(str, n)) for n in SHORT_X])
 def test_xi_sweep_short_lines(n, recon, prec):
-    case = G.periodic_case(3, n, 6)
+    nd = len(n)
+    case = G.periodic_case(nd, n, 6)
     og, fg = grids(case)
     met = O.metrics(og, 6, case["xyz"])
     fsc = fp.Scheme(recon, 6, True, precision=prec)
     mg, qg = dev(met), dev(case["q"])
     F = host(fp.face_fluxes(fg, fsc, mg, qg, 0))
     acc = torch.zeros_like(qg)
-    got = interior(host(fp.residual_dir(fg, fsc, mg, qg, 0, acc)), 3, 3)
+    got = interior(host(fp.residual_dir(fg, fsc, mg, qg, 0, acc)), 3, nd)
     assert relerr(got, -(F[..., 1:] - F[..., :-1])) <= 1e-9
     ref = O.residual(og, O.Scheme(recon, 6, True), met, case["q"])
     res = host(fp.residual(fg, fsc, mg, qg))
-    assert relerr(interior(res, 3, 3), interior(ref, 3, 3)) <= (1e-11 if prec == "fp64" else 1e-4)
+    assert relerr(interior(res, 3, nd), interior(ref, 3, nd)) <= (1e-11 if prec == "fp64" else 1e-4)
 
 
 # Accumulating direction residuals: with accumulate set, each direction adds
