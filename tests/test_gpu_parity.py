@@ -144,6 +144,30 @@ def test_xi_sweep_short_lines(n, recon, prec):
     assert relerr(interior(res, 3, nd), interior(ref, 3, nd)) <= (1e-11 if prec == "fp64" else 1e-4)
 
 
+# The same for the wide stencils (WENO7, eighth-order metrics; ghost 4),
+# whose sweeps stage 128 entries in both precisions.
+SHORT_X_WIDE = [(4, 5, 6), (13, 4, 4), (29, 5, 4), (61, 4, 4), (4, 5), (29, 6), (67, 4)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("recon,Y", [("weno7", 8), ("weno7", 6), ("weno5", 8)])
+@pytest.mark.parametrize("n", SHORT_X_WIDE, ids=["x".join(map(str, n)) for n in SHORT_X_WIDE])
+def test_xi_sweep_short_lines_wide(n, recon, Y, prec):
+    nd = len(n)
+    case = G.periodic_case(nd, n, Y, g=4)
+    og, fg = grids(case)
+    met = O.metrics(og, Y, case["xyz"])
+    fsc = fp.Scheme(recon, Y, True, precision=prec)
+    mg, qg = dev(met), dev(case["q"])
+    F = host(fp.face_fluxes(fg, fsc, mg, qg, 0))
+    acc = torch.zeros_like(qg)
+    got = interior(host(fp.residual_dir(fg, fsc, mg, qg, 0, acc)), 4, nd)
+    assert relerr(got, -(F[..., 1:] - F[..., :-1])) <= 1e-9
+    ref = O.residual(og, O.Scheme(recon, Y, True), met, case["q"])
+    res = host(fp.residual(fg, fsc, mg, qg))
+    assert relerr(interior(res, 4, nd), interior(ref, 4, nd)) <= (1e-11 if prec == "fp64" else 1e-4)
+
+
 # Accumulating direction residuals: with accumulate set, each direction adds
 # its flux difference to what the array holds (the xi sweep then runs its
 # accumulating kernel variant), so the result is the held values plus the
