@@ -11,14 +11,15 @@
 // Occupancy target of the face kernels: two waves per SIMD fits the FP64
 // WENO face (the 6-node x 5-field characteristic values dominate) without
 // spilling.  The FP32-mixed xi sweeps of the six-point stencils (WENO5,
-// LU5, WENOCU6 with metrics of order up to 6) fit three (at most 168
-// registers) and run at three: their LDS window buffers allow it, the
-// eta/zeta rings (72 KB per workgroup) do not; WENO7 and eighth-order
-// metrics would spill at three.
+// LU5, WENOCU6 with metrics of order up to 6) and the FP64 LU5 ones fit
+// three (at most 168 registers) and run at three: their LDS window buffers
+// allow it, the eta/zeta rings (72 KB per workgroup) do not; WENO7 and
+// eighth-order metrics would spill at three.
 #ifndef FP_SWEEP_ATTR
 #define FP_SWEEP_ATTR __attribute__((amdgpu_waves_per_eu(2, 2)))
 #endif
-#define FP_XWAVES(PREC, RECON, Y) (((PREC) == 1 && (RECON) != 2 && (Y) != 8) ? 3 : 2)
+#define FP_XWAVES(PREC, RECON, Y) \
+    ((((PREC) == 1 && (RECON) != 2) || ((PREC) == 0 && (RECON) == 1)) && (Y) != 8 ? 3 : 2)
 #define FP_XSWEEP_ATTR(PREC, RECON, Y) \
     __attribute__((amdgpu_waves_per_eu(FP_XWAVES(PREC, RECON, Y), FP_XWAVES(PREC, RECON, Y))))
 
