@@ -116,7 +116,7 @@ def test_face_fluxes_and_residual(ndim, n, Y, recon, reform, state):
 
 # Short xi lines: the xi sweep packs the faces of consecutive lines into
 # items of at most 64, as many as the staged window holds (88 entries for the
-# FP32-mixed six-point stencils, 128 for the others), so lines of a few nodes
+# FP32-mixed six-point stencils and FP64 LU5, 128 for the others), so lines of a few nodes
 # give items of many short lines and lines under 30 nodes items of fewer than
 # 64 faces.  Every xi difference of the sweep is the difference of the
 # face-flux kernel's fluxes (the same face code, one lane per face), and the
