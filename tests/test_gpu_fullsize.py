@@ -14,6 +14,10 @@ benchmark times.
 * The same grid and state with the sixth-order viscous fluxes (mu 1e-3,
   Prandtl 0.72): the Navier-Stokes residual at every interior node against
   the oracle's, both from the oracle's metrics (bars as at small sizes).
+* The same grid and state, WENO5-JS with sixth-order metrics: one full RK3
+  step of the 256^3 block at every node from identical inputs (the oracle's
+  metrics on both sides), FP64 at 1e-12 per variable and the FP32-mixed
+  form against the same FP64 oracle step at 1e-4 of the step's increment.
 * The same grid cut into 2 x 2 x 2 linked 128^3 blocks, advanced by the
   batched path as its benchmark runs it (FP32-mixed, autotuned segments):
   bitwise the single 256^3 block after two RK3 steps.
@@ -163,6 +167,41 @@ def c3_grid_and_state(n=256, g=3, Y=6, L=12.0):
     vel = I.mach_velocity(0.8, I.direction_3d())
     q = I.Vortex(vel_inf=tuple(vel)).state(I.state_nodes(xyz, g, Y), period=L)
     return xyz, q
+
+
+def test_c3_256_full_rk3_step_same_inputs():
+    """The benchmarked 256^3 block, one RK3 step at every node: the FP64
+    path within 1e-12 per variable of the oracle, the FP32-mixed path within
+    1e-4 of the step's increment (the characteristic arithmetic runs in
+    FP32 on reference-subtracted values, about 1e-7 of their size, and the
+    nonlinear weights amplify that by their sensitivity to the smoothness
+    indicators)."""
+    n, g, Y = 256, 3, 6
+    xyz, q = c3_grid_and_state(n, g, Y)
+    og, fg = O.Grid(3, n, g), fp.Grid(3, n, g)
+    met = O.metrics(og, Y, xyz)
+    del xyz
+    osc = O.Scheme("weno5", Y, True)
+    dt = O.max_dt(og, osc, met, q, 0.5)
+    print(f"C3 256^3 WENO5-M6, one RK3 step, dt {dt:.4e}", flush=True)
+    ref = O.rk3_step(og, osc, met, q, dt)
+    mg = dev(met)
+    del met
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    qg = dev(q)
+    fp.rk3_step(fg, fp.Scheme("weno5", Y, True), mg, qg, work, dt)
+    got = host(qg)
+    err = relerr(interior(got, g, 3), interior(ref, g, 3))
+    print(f"C3 256^3 FP64 step vs oracle: {err:.2e}", flush=True)
+    assert err <= 1e-12
+    qg.copy_(dev(q))
+    fp.rk3_step(fg, fp.Scheme("weno5", Y, True, precision="mixed"), mg, qg, work, dt)
+    got = host(qg)
+    inc = (interior(ref, g, 3) - interior(q, g, 3)).reshape(5, -1)
+    diff = (interior(got, g, 3) - interior(ref, g, 3)).reshape(5, -1)
+    rel = [float(np.abs(diff[v]).max() / np.abs(inc[v]).max()) for v in range(5)]
+    print(f"C3 256^3 mixed step vs FP64 oracle, per variable, of the increment: {rel}", flush=True)
+    assert max(rel) <= 1e-4
 
 
 def test_c3v_256_navier_stokes_residual_every_node():

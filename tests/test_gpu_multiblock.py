@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from paper_2101_05886_amd import fp
 from tests import gpu_cases as G
 
@@ -94,6 +95,60 @@ def test_2d_grid_cut_3x2_lu5():
 def test_weno7_m8_cut_2x1():
     case = G.periodic_case(3, (40, 28, 20), 8, g=4, state="noisy", seed=43)
     decompose(case, (2, 1), 8, "weno7", "mixed", 2)
+
+
+@pytest.mark.parametrize("ndim,n,cuts,Y,recon", [(3, (48, 40, 24), (2, 2), 6, "weno5"),
+                                                 (2, (66, 40), (3, 2), 4, "linup5")])
+def test_linked_blocks_match_oracle_on_undivided_grid(ndim, n, cuts, Y, recon):
+    """The linked pieces against the FP64 oracle advancing the undivided
+    periodic grid.  Each piece takes its slice of the oracle's metrics of the
+    whole grid (its ghost layers are then the neighbours' interior metrics,
+    which the link setup copies in), so both sides start from identical
+    inputs: FP64 within 1e-12 per variable after one RK3 step and 3e-12
+    after three; FP32-mixed within 1e-4 of the increment after one step."""
+    case = G.periodic_case(ndim, n, Y, state="noisy", seed=44)
+    g = case["g"]
+    og = O.Grid(ndim, n, g)
+    met = O.metrics(og, Y, case["xyz"])
+    osc = O.Scheme(recon, Y, True)
+    dt = 0.5 * O.max_dt(og, osc, met, case["q"], 1.0)
+    ref1 = O.rk3_step(og, osc, met, case["q"], dt)
+    ref3 = O.solve(og, osc, met, case["q"], dt, 3)
+    sizes = [n[d] // cuts[d] if d < 2 else n[d] for d in range(ndim)]
+    grid_cuts = [cuts[d] if d < 2 else 1 for d in range(ndim)]
+    for prec, steps, ref in (("fp64", 1, ref1), ("fp64", 3, ref3), ("mixed", 1, ref1)):
+        sc = fp.Scheme(recon, Y, True, precision=prec)
+        pieces, index = [], {}
+        for c in np.ndindex(*grid_cuts):
+            lo = [c[d] * sizes[d] for d in range(ndim)]
+            sl = (slice(None),) + tuple(slice(lo[d], lo[d] + sizes[d] + 2 * g) for d in reversed(range(ndim)))
+            bc = [FROZEN if d < 2 else PERIODIC for d in range(ndim)]
+            Gp = fp.Grid(ndim, sizes, g, bc=bc)
+            index[c] = len(pieces)
+            pieces.append((Gp, dev(met[sl]), dev(case["q"][sl]),
+                           torch.zeros(Gp.work_shape(), dtype=torch.float64, device="cuda"), dt, lo))
+        links = []
+        for c, i in index.items():
+            for d in range(2):
+                for side in (0, 1):
+                    nb = list(c)
+                    nb[d] = (c[d] + (1 if side else -1)) % grid_cuts[d]
+                    links.append((i, d, side, index[tuple(nb)]))
+        b = fp.Batch(sc, len(pieces))
+        b.set([p[:5] for p in pieces])
+        b.set_links(links)
+        b.solve(steps)
+        torch.cuda.synchronize()
+        for Gp, mp, qp, work, _, lo in pieces:
+            sl = (slice(None),) + tuple(slice(g + lo[d], g + lo[d] + sizes[d]) for d in reversed(range(ndim)))
+            got = qp.cpu().numpy()[(slice(None),) + (slice(g, -g),) * ndim].reshape(len(ref), -1)
+            want = ref[sl].reshape(len(ref), -1)
+            base = want if prec == "fp64" else want - case["q"][sl].reshape(len(ref), -1)
+            bar = 1e-12 * steps if prec == "fp64" else 1e-4
+            for v in range(len(ref)):
+                err = np.abs(got[v] - want[v]).max() / np.abs(base[v]).max()
+                assert err <= bar, f"{prec} {steps} steps, piece at {lo}, variable {v}: {err:.3e}"
+        b.close()
 
 
 def test_links_are_validated():

@@ -89,6 +89,7 @@ FLUX_CASES = [
     (3, (17, 20, 13), 6, "linup5", 1, "noisy"),
     (3, (16, 16, 16), 8, "weno5", 1, "vortex"),
     (3, (19, 16, 15), 4, "weno5", 0, "noisy"),
+    (3, (18, 17, 15), 4, "linup5", 1, "noisy"),
 ]
 
 
@@ -144,6 +145,34 @@ def test_xi_sweep_short_lines(n, recon, prec):
     assert relerr(interior(res, 3, nd), interior(ref, 3, nd)) <= (1e-11 if prec == "fp64" else 1e-4)
 
 
+# Linear upwind with fourth-order metrics: its xi sweep takes the same
+# three-wave, 88-entry path as with sixth-order metrics in both precisions.
+SHORT_X_M4 = [(3, 4, 5), (29, 5, 3), (30, 4, 4), (67, 3, 3), (13, 4), (67, 3)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n", SHORT_X_M4, ids=["x".join(map(str, n)) for n in SHORT_X_M4])
+def test_xi_sweep_short_lines_lu5_m4(n, prec):
+    nd = len(n)
+    case = G.periodic_case(nd, n, 4, state="noisy")
+    og, fg = grids(case)
+    met = O.metrics(og, 4, case["xyz"])
+    fsc = fp.Scheme("linup5", 4, True, precision=prec)
+    mg, qg = dev(met), dev(case["q"])
+    F = host(fp.face_fluxes(fg, fsc, mg, qg, 0))
+    got = interior(host(fp.residual_dir(fg, fsc, mg, qg, 0, torch.zeros_like(qg))), 3, nd)
+    assert relerr(got, -(F[..., 1:] - F[..., :-1])) <= 1e-9
+    ref = O.residual(og, O.Scheme("linup5", 4, True), met, case["q"])
+    res = host(fp.residual(fg, fsc, mg, qg))
+    assert relerr(interior(res, 3, nd), interior(ref, 3, nd)) <= (1e-11 if prec == "fp64" else 1e-4)
+    if prec == "fp64":
+        dt = 0.5 * O.max_dt(og, O.Scheme("linup5", 4, True), met, case["q"], 1.0)
+        refq = O.rk3_step(og, O.Scheme("linup5", 4, True), met, case["q"], dt)
+        work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+        fp.rk3_step(fg, fsc, mg, qg, work, dt)
+        assert relerr(interior(host(qg), 3, nd), interior(refq, 3, nd)) <= 1e-12
+
+
 # The same for the wide stencils (WENO7, eighth-order metrics; ghost 4),
 # whose sweeps stage 128 entries in both precisions.
 SHORT_X_WIDE = [(4, 5, 6), (13, 4, 4), (29, 5, 4), (61, 4, 4), (4, 5), (29, 6), (67, 4)]
@@ -195,7 +224,7 @@ def test_residual_dir_accumulates(ndim, n, prec):
 
 
 RK_CASES = [(2, (70, 45), 2, "weno5"), (2, (64, 64), 6, "linup5"), (3, (21, 18, 16), 6, "weno5"),
-            (3, (20, 20, 20), 2, "linup5")]
+            (3, (20, 20, 20), 2, "linup5"), (3, (20, 18, 16), 4, "linup5")]
 
 
 @pytest.mark.parametrize("ndim,n,Y,recon", RK_CASES)
@@ -310,6 +339,40 @@ def test_deterministic_bitwise():
     a = host(fp.residual(fg, sc, mg, qg))
     b = host(fp.residual(fg, sc, mg, qg))
     assert np.array_equal(a, b)
+
+
+def test_tangent_tie_faces_match_oracle():
+    """A grid symmetric under the swap of y and z (the unjittered wavy
+    mapping with n_eta = n_zeta): on the xi-lines with j = k the xi-face
+    normals have |n_y| = |n_z| analytically, the two smallest components, so
+    the tangent basis is decided by the tie rule (lowest axis wins within
+    1e-10), not by rounding.  A different choice rotates the shear fields and
+    changes the WENO fluxes far above the bar, so FP64 parity on a
+    non-uniform state shows that both sides take the same basis.  The mixed
+    path decides on FP32 normals, where 1e-10 is below one ulp: analytic ties
+    round to equal FP32 values and take the same axis."""
+    case = G.periodic_case(3, (20, 16, 16), 6, state="noisy", jitter=0.0, seed=9)
+    og, fg = grids(case)
+    met = O.metrics(og, 6, case["xyz"])
+    # xi-face metrics by the sixth-order face interpolation, on the j = k lines
+    w = np.array([1, -8, 37, 37, -8, 1]) / 60.0
+    g = case["g"]
+    s = met[0:3]
+    sf = sum(w[r] * s[..., r:r + s.shape[-1] - 5] for r in range(6))  # faces i-1/2 .. over the x extent
+    j = np.arange(16)
+    ny, nz = np.abs(sf[1, g + j, g + j]), np.abs(sf[2, g + j, g + j])
+    nx = np.abs(sf[0, g + j, g + j])
+    assert np.all(np.minimum(ny, nz) < nx)
+    gap = np.abs(ny - nz) / np.sqrt(sf[0, g + j, g + j] ** 2 + ny ** 2 + nz ** 2)
+    assert np.all(gap < 1e-13)
+    mg, qg = dev(met), dev(case["q"])
+    ref = O.face_fluxes(og, O.Scheme("weno5", 6, True), met, case["q"], 0)
+    got = host(fp.face_fluxes(fg, fp.Scheme("weno5", 6, True), mg, qg, 0))
+    assert relerr(got, ref) <= 1e-12
+    diag = (slice(None), j, j)  # the flux arrays hold interior lines only
+    assert relerr(got[diag], ref[diag]) <= 1e-12
+    mixed = host(fp.face_fluxes(fg, fp.Scheme("weno5", 6, True, precision="mixed"), mg, qg, 0))
+    assert relerr(mixed[diag], ref[diag]) <= 1e-5
 
 
 def test_max_dt_and_check_state():
