@@ -170,12 +170,20 @@ class Scheduler:
         used = 0
         inflight = None  # (token, finished slots) of the last enqueued round
         changed = True
+        released = False  # finished requests the batch may still reference
         b.start()
         while pending or queue or active:
             now = b.now()
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             b.prefetch(queue[: self.prefetch])
+            if released:
+                # the batch drops its references to the retired requests'
+                # buffers before new ones are allocated, so device use stays
+                # within the budget that `used` accounts for
+                b.set_active([s.handle for s in active])
+                released = False
+                changed = False
             # admission: first fit, in arrival order, by footprint and slots
             i = 0
             while i < len(queue) and len(active) < self.max_active:
@@ -218,6 +226,7 @@ class Scheduler:
             for s in done:
                 results[s.req.rid] = b.retire(s.handle)
                 used -= s.footprint
+                released = True
             token = b.round_end()
             st.rounds += 1
             if inflight is not None:

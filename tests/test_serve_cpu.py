@@ -157,3 +157,48 @@ def test_oversized_request_is_an_error():
     r = S.Request(0, 0.0, "wavy3d", (100, 100, 100), 0.5, 0.0, 10)
     with pytest.raises(ValueError):
         run([r], budget=1000)
+
+
+class HeldBackend(SimBackend):
+    """Device memory as the GPU backend holds it: a retired request's
+    buffers stay allocated while the batch still references them, i.e.
+    until the next set_active that leaves them out."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.held = set()
+
+    def set_active(self, handles):
+        keep = {r.rid for r in handles}
+        for rid in list(self.held):
+            if rid not in keep:
+                self.held.discard(rid)
+                self.allocated -= self.fp[rid]
+        super().set_active(handles)
+
+    def admit(self, r):
+        self.fp = getattr(self, "fp", {})
+        self.fp[r.rid] = self.footprint(r)
+        return super().admit(r)
+
+    def retire(self, r):
+        out = super().retire(r)
+        self.allocated += self.footprint(r)  # not freed yet
+        self.held.add(r.rid)
+        return out
+
+
+def test_retired_buffers_are_released_before_admission():
+    # a tight budget and a steady stream: every admission follows a
+    # retirement, so device use would exceed the budget if the batch still
+    # held the retired requests' buffers when new ones are allocated
+    reqs = S.make_requests(60, seed=12, rate=None, nodes_range=(30000, 300000), steps=25)
+    for i, r in enumerate(reqs):
+        r.steps = 10 + (i * 13) % 37
+    budget = 150 * 10 ** 6
+    be = HeldBackend()
+    st, res = S.Scheduler(be, budget, 8, 10).run(reqs)
+    assert len(res) == len(reqs)
+    assert be.peak <= budget
+    for r in reqs:
+        assert be.steps[r.rid] == r.steps
