@@ -170,6 +170,25 @@ fp_status fp_residual_dir(const fp_grid *grid, const fp_scheme *scheme, const do
 fp_status fp_rk3_step(const fp_grid *grid, const fp_scheme *scheme, const double *met,
                       double *q, double *work, double dt, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step
+ * of fp_rk3_step with its workspace in static device memory of the library
+ * instead of a caller buffer.  Each GPU the library runs on holds one
+ * FP_NOALLOC_WORK_BYTES array from the first call on that GPU until the
+ * process ends; the call itself allocates nothing.  Grids whose
+ * fp_work_bytes exceeds FP_NOALLOC_WORK_BYTES are rejected with FP_EINVAL
+ * before anything is enqueued (64 MiB: up to 76^3 interior nodes in 3D,
+ * 830^2 in 2D, with ghost 3).  Every call on one GPU shares that array, so calls that
+ * overlap on one GPU (on different streams, or from several threads without
+ * ordering) race and give undefined results; calls in one stream order are
+ * safe.  The array keeps the last call's contents; a step writes every
+ * workspace value it reads before reading it (stage registers, their frozen
+ * ghost layers, the residual accumulator, the global speed sets), so no
+ * clearing is needed.  Results are bitwise those of fp_rk3_step. */
+#define FP_NOALLOC_WORK_BYTES ((size_t)64 << 20)
+fp_status fp_rk3_step_noalloc(const fp_grid *grid, const fp_scheme *scheme, const double *met,
+                              double *q, double dt, void *stream);
+
 /* nsteps RK3 steps of fixed dt.  The first call for a given (grid, scheme,
  * pointers, dt) captures the stages of one step into a HIP graph that later
  * calls replay; the frozen ghost layers are copied into the stage registers

@@ -398,6 +398,37 @@ hipError_t run_rk3(const Ctx& c, const double* met, double* q, double* work, dou
     return hipSuccess;
 }
 
+// ---- workspace of fp_rk3_step_noalloc ----
+
+// Static device memory, one copy per GPU, held until the process ends.  In
+// host code `scratch` names a host-side stand-in, never the device array:
+// the device address is fetched per device with hipGetSymbolAddress and
+// only that pointer is passed to kernels.
+static __device__ __align__(256) double scratch[FP_NOALLOC_WORK_BYTES / sizeof(double)];
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;
+
+// the device address of `scratch` on the current device (fetched on the
+// first call on that device, with it current)
+fp_status scratch_ptr(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return FP_OK;
+    }
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress (no-allocation workspace)");
+    if (!p) return fail(FP_EHIP, "hipGetSymbolAddress returned NULL for the no-allocation workspace");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+    *out = static_cast<double*>(p);
+    return FP_OK;
+}
+
 // ---- step graph cache of fp_solve ----
 
 struct GraphKey {
@@ -794,6 +825,28 @@ fp_status fp_rk3_step(const fp_grid* g, const fp_scheme* sch, const double* met,
     if (st) return st;
     hipError_t e = run_rk3(c, met, q, work, dt, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fp_rk3_step launch");
+    return FP_OK;
+}
+
+fp_status fp_rk3_step_noalloc(const fp_grid* g, const fp_scheme* sch, const double* met, double* q, double dt,
+                              void* stream) {
+    Ctx c;
+    fp_status st = make_ctx(g, sch, c);
+    if (st) return st;
+    if (sch->mu > 0.0) return fail(FP_EUNSUPPORTED, "viscous schemes take fp_viscous_residual / fp_solve_ns");
+    if (!met || !q) return fail(FP_EINVAL, "NULL array");
+    if (!(dt > 0.0)) return fail(FP_EINVAL, "dt must be positive");
+    const size_t need = fp_work_bytes(g);
+    if (need > FP_NOALLOC_WORK_BYTES)
+        return fail(FP_EINVAL, "grid needs %zu bytes of workspace; fp_rk3_step_noalloc holds %zu (use fp_rk3_step)",
+                    need, (size_t)FP_NOALLOC_WORK_BYTES);
+    st = bind_speeds(c.sk);
+    if (st) return st;
+    double* work = nullptr;
+    st = scratch_ptr(&work);
+    if (st) return st;
+    hipError_t e = run_rk3(c, met, q, work, dt, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fp_rk3_step_noalloc launch");
     return FP_OK;
 }
 

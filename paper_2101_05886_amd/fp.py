@@ -23,7 +23,8 @@ FP_LLF, FP_GLF = 0, 1
 FP_FACE_HOLD, FP_FACE_EXTRAP, FP_FACE_WALL, FP_FACE_SHOCK = 0, 1, 2, 3
 
 EXPORTS = ["fp_state_bytes", "fp_metric_bytes", "fp_coord_bytes", "fp_work_bytes", "fp_metrics",
-           "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve", "fp_max_dt",
+           "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_rk3_step_noalloc", "fp_solve",
+           "fp_max_dt",
            "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step", "fp_batch_solve",
            "fp_batch_set_links", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error",
            "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_work_bytes", "fp_viscous_residual", "fp_solve_ns",
@@ -84,6 +85,7 @@ def lib():
         L.fp_residual.argtypes = [gp, sp, dp, dp, dp, vp]
         L.fp_residual_dir.argtypes = [gp, sp, dp, dp, C.c_int32, dp, C.c_int32, vp]
         L.fp_rk3_step.argtypes = [gp, sp, dp, dp, dp, C.c_double, vp]
+        L.fp_rk3_step_noalloc.argtypes = [gp, sp, dp, dp, C.c_double, vp]
         L.fp_solve.argtypes = [gp, sp, dp, dp, dp, C.c_double, C.c_int64, vp]
         L.fp_max_dt.argtypes = [gp, sp, dp, dp, C.c_double, dp, vp]
         L.fp_apply_bcs.argtypes = [gp, C.POINTER(FPBcs), dp, dp, C.c_double, vp]
@@ -108,7 +110,8 @@ def lib():
         L.fp_release_cache.argtypes = []
         L.fp_release_cache.restype = None
         L.fp_last_error.restype = C.c_char_p
-        for name in ("fp_metrics", "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_solve",
+        for name in ("fp_metrics", "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step",
+                     "fp_rk3_step_noalloc", "fp_solve",
                      "fp_max_dt", "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step",
                      "fp_batch_solve", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_set_links",
                      "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_residual", "fp_solve_ns", "fp_profile_step"):
@@ -323,6 +326,19 @@ def rk3_step(grid: Grid, scheme: Scheme, met, q, work, dt: float) -> torch.Tenso
     _check(lib().fp_rk3_step(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
                              _dev(q, state_bytes(grid), "q"), _dev(work, work_bytes(grid), "work"),
                              float(dt), _stream()))
+    return q
+
+
+# the workspace limit of fp_rk3_step_noalloc (FP_NOALLOC_WORK_BYTES in fp.h)
+NOALLOC_WORK_BYTES = 64 << 20
+
+
+def rk3_step_noalloc(grid: Grid, scheme: Scheme, met, q, dt: float) -> torch.Tensor:
+    """fp_rk3_step with the library's static per-GPU workspace (no device
+    allocation by the caller or the library)."""
+    g, s = grid.c(), scheme.c()
+    _check(lib().fp_rk3_step_noalloc(C.byref(g), C.byref(s), _dev(met, metric_bytes(grid), "met"),
+                                     _dev(q, state_bytes(grid), "q"), float(dt), _stream()))
     return q
 
 

@@ -121,3 +121,23 @@ def test_zero_steps_is_a_no_op_before_any_device_call():
     p = C.c_void_p(16)  # never dereferenced: nothing is launched for zero steps
     assert L.fp_solve(C.byref(g), C.byref(s), p, p, p, 0.1, 0, None) == fp.FP_OK
     assert L.fp_solve(C.byref(g), C.byref(s), p, p, p, 0.1, -1, None) == fp.FP_EINVAL
+
+
+def test_noalloc_step_rejects_grids_beyond_its_workspace():
+    # checked before any device call: fp_work_bytes above the static
+    # workspace (64 MiB) is FP_EINVAL with a message naming both sizes
+    L = fp.lib()
+    assert fp.NOALLOC_WORK_BYTES == 64 << 20
+    text = open(os.path.join(ROOT, "include", "fp.h")).read()
+    assert "#define FP_NOALLOC_WORK_BYTES ((size_t)64 << 20)" in text
+    fits = fp.Grid(3, (76, 76, 76), 3)
+    assert fp.work_bytes(fits) <= fp.NOALLOC_WORK_BYTES
+    big = fp.Grid(3, (77, 77, 77), 3)
+    assert fp.work_bytes(big) > fp.NOALLOC_WORK_BYTES
+    g, sc = big.c(), fp.Scheme().c()
+    p = C.c_void_p(16)  # never dereferenced: the size check fails first
+    assert L.fp_rk3_step_noalloc(C.byref(g), C.byref(sc), p, p, 0.1, None) == fp.FP_EINVAL
+    assert b"fp_rk3_step_noalloc holds" in L.fp_last_error()
+    g2 = fp.Grid(3, (8, 8, 8), 3).c()
+    assert L.fp_rk3_step_noalloc(C.byref(g2), C.byref(sc), None, None, 0.1, None) == fp.FP_EINVAL
+    assert L.fp_rk3_step_noalloc(C.byref(g2), C.byref(sc), p, p, -1.0, None) == fp.FP_EINVAL
