@@ -110,50 +110,63 @@ __device__ __forceinline__ constexpr double iw(int r) {
     }
 }
 
-// WENO5-JS of a 5-point window a..e (face between c and d, upwind side a).
-// Weights C_k/(beta_k+eps)^2 normalised over one common denominator.
+// WENO5-JS of a 5-point window a..e (face between c and d, upwind side a),
+// in a scaled form.  The window holds twice the split values and eps16 is
+// 16 eps: the indicators are evaluated as 4 beta_k = 13/3 t^2 + s^2 of the
+// doubled window, i.e. 16 beta_k of the split values, so with 16 eps every
+// weight is that of the split values (powers of two: exact), and the
+// result is twice their reconstruction.  (The flux splitting's 1/2 is
+// applied once, after the back-projection.)  The optimal weights
+// C = (1/10, 3/5, 3/10) are folded into the candidates' constants:
+// c_k = C_k (6 q_k), and the denominator carries 6 C_k.
+// FP64: weights C_k/(beta_k+eps)^2 normalised over one common denominator
+// (products of the squared indicators), one reciprocal per reconstruction.
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e,
-                                        double eps) {
-    const double q0 = 2.0 * a - 7.0 * b + 11.0 * c;
-    const double q1 = -b + 5.0 * c + 2.0 * d;
-    const double q2 = 2.0 * c + 5.0 * d - e;
+                                        double eps16) {
+    const double c0 = 0.2 * a - 0.7 * b + 1.1 * c;
+    const double c1 = -0.6 * b + 3.0 * c + 1.2 * d;
+    const double c2 = 0.6 * c + 1.5 * d - 0.3 * e;
     const double t0 = a - 2.0 * b + c, s0 = a - 4.0 * b + 3.0 * c;
     const double t1 = b - 2.0 * c + d, s1 = d - b;
     const double t2 = c - 2.0 * d + e, s2 = 3.0 * c - 4.0 * d + e;
-    const double k13 = 13.0 / 12.0;
-    double d0 = k13 * t0 * t0 + 0.25 * s0 * s0 + eps;
-    double d1 = k13 * t1 * t1 + 0.25 * s1 * s1 + eps;
-    double d2 = k13 * t2 * t2 + 0.25 * s2 * s2 + eps;
+    const double k = 13.0 / 3.0;
+    double d0 = fma(k * t0, t0, fma(s0, s0, eps16));
+    double d1 = fma(k * t1, t1, fma(s1, s1, eps16));
+    double d2 = fma(k * t2, t2, fma(s2, s2, eps16));
     d0 *= d0;
     d1 *= d1;
     d2 *= d2;
-    const double a0 = 0.1 * (d1 * d2), a1 = 0.6 * (d0 * d2), a2 = 0.3 * (d0 * d1);
-    return (a0 * q0 + a1 * q1 + a2 * q2) * drcp(6.0 * (a0 + a1 + a2));
+    const double p0 = d1 * d2, p1 = d0 * d2, p2 = d0 * d1;
+    const double num = fma(p0, c0, fma(p1, c1, p2 * c2));
+    const double den = fma(p0, 0.6, fma(p1, 3.6, p2 * 1.8));
+    return num * drcp1(den);
 }
 
 // FP32 form: reciprocal weights (no overflow of the products for large beta)
-__device__ __forceinline__ float weno5(float a, float b, float c, float d, float e, float eps) {
-    const float q0 = 2.0f * a - 7.0f * b + 11.0f * c;
-    const float q1 = -b + 5.0f * c + 2.0f * d;
-    const float q2 = 2.0f * c + 5.0f * d - e;
+__device__ __forceinline__ float weno5(float a, float b, float c, float d, float e, float eps16) {
+    const float c0 = 0.2f * a - 0.7f * b + 1.1f * c;
+    const float c1 = -0.6f * b + 3.0f * c + 1.2f * d;
+    const float c2 = 0.6f * c + 1.5f * d - 0.3f * e;
     const float t0 = a - 2.0f * b + c, s0 = a - 4.0f * b + 3.0f * c;
     const float t1 = b - 2.0f * c + d, s1 = d - b;
     const float t2 = c - 2.0f * d + e, s2 = 3.0f * c - 4.0f * d + e;
-    const float k13 = 13.0f / 12.0f;
-    float d0 = k13 * t0 * t0 + 0.25f * s0 * s0 + eps;
-    float d1 = k13 * t1 * t1 + 0.25f * s1 * s1 + eps;
-    float d2 = k13 * t2 * t2 + 0.25f * s2 * s2 + eps;
-    const float a0 = 0.1f * fast_rcp(d0 * d0);
-    const float a1 = 0.6f * fast_rcp(d1 * d1);
-    const float a2 = 0.3f * fast_rcp(d2 * d2);
-    return (a0 * q0 + a1 * q1 + a2 * q2) * fast_rcp(6.0f * (a0 + a1 + a2));
+    const float k = 13.0f / 3.0f;
+    const float d0 = fmaf(k * t0, t0, fmaf(s0, s0, eps16));
+    const float d1 = fmaf(k * t1, t1, fmaf(s1, s1, eps16));
+    const float d2 = fmaf(k * t2, t2, fmaf(s2, s2, eps16));
+    const float r0 = fast_rcp(d0 * d0), r1 = fast_rcp(d1 * d1), r2 = fast_rcp(d2 * d2);
+    const float num = fmaf(r0, c0, fmaf(r1, c1, r2 * c2));
+    const float den = fmaf(r0, 0.6f, fmaf(r1, 3.6f, r2 * 1.8f));
+    return num * fast_rcp(den);
 }
 
 // WENO7-JS of a 7-point window v[0..6] (face between v[3] and v[4], upwind
 // side v[0]): four cubic candidates, optimal weights (1, 12, 18, 4)/35,
 // smoothness indicators as the integer quadratic forms (240 x the Jiang-Shu
 // measure), weights C_k/(beta_k+eps)^2 from reciprocals (the indicators can
-// be large, so no common-denominator products).
+// be large, so no common-denominator products).  Called on twice the split
+// values with 4 eps, it returns twice their reconstruction (the indicators
+// are quadratic: exact).
 template <typename T>
 __device__ __forceinline__ T weno7(const T (&v)[7], T eps) {
     const T a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5], g = v[6];
@@ -196,6 +209,8 @@ __device__ __forceinline__ T weno7(const T (&v)[7], T eps) {
 // tau6 = beta6 - (beta_0 + 4 beta_1 + beta_2)/6, evaluated as
 // ((C m + tau6 m/(beta_k+eps)) / (m + |tau6|))^2 with m = min_k (beta_k+eps):
 // the same ratios, every factor in [-C, C], so no overflow for any eps.
+// Called on twice the split values with 4 eps, it returns twice their
+// reconstruction (indicators and tau6 are quadratic: exact).
 template <typename T>
 __device__ __forceinline__ T wenocu6(const T (&v)[6], T eps) {
     const T a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5];
@@ -307,7 +322,10 @@ __device__ __forceinline__ void face_ref(const LD& ld, const SchemeK& sk, FaceRe
 template <int DIM, typename T>
 struct Eig {
     T n[DIM], uh[DIM], t1[DIM], t2[3];
-    T un, Hh, ch, ic, b2, hq2, ut1, ut2, sigma;
+    T un, Hh, ch, hq2, ut1, ut2, sigma;
+    // the projection's scales, halved: with b2 = (gamma-1)/c^2 and ic = 1/c,
+    // pB = b2/2 and pI = ic/2
+    T pB, pI;
 };
 
 template <int DIM, typename T, class LD>
@@ -358,10 +376,11 @@ __device__ __forceinline__ void roe(const LD& ld, const SchemeK& sk, const FaceR
     S.un = un;
     S.Hh = (wL * T(HL) + wR * T(HR)) * iwr;
     const T c2 = T(gm1) * (S.Hh - T(0.5) * q2);
-    S.ic = rsq1<T>(c2);
-    S.ch = c2 * S.ic;
-    S.b2 = T(gm1) * (S.ic * S.ic);
+    const T ic = rsq1<T>(c2);
+    S.ch = c2 * ic;
     S.hq2 = T(0.5) * q2;
+    S.pB = T(0.5 * gm1) * (ic * ic);
+    S.pI = T(0.5) * ic;
     if constexpr (DIM == 2) {
         S.t1[0] = -S.n[1];
         S.t1[1] = S.n[0];
@@ -438,7 +457,8 @@ __device__ __forceinline__ void node_diff(const LD& ld, int r, const SchemeK& sk
 // l_s . w for the five (four in 2D) fields, using the structure of the Euler
 // eigenvectors: l_0 w = (phi - psi)/2, l_1 w = w_0 - phi, l_t w = t.w_m -
 // (u.t) w_0, l_E w = (phi + psi)/2 with phi = b2 (|u|^2/2 w_0 - u.w_m + w_E)
-// and psi = (n.w_m - u_n w_0)/c.
+// and psi = (n.w_m - u_n w_0)/c; evaluated as phi/2 and psi/2 with the
+// halved scales of Eig.
 template <int DIM, typename T>
 __device__ __forceinline__ void project(const Eig<DIM, T>& S, const T (&w)[DIM + 2],
                                         T (&a)[DIM + 2]) {
@@ -451,13 +471,13 @@ __device__ __forceinline__ void project(const Eig<DIM, T>& S, const T (&w)[DIM +
         t1w += S.t1[c] * w[1 + c];
         if constexpr (DIM == 3) t2w += S.t2[c] * w[1 + c];
     }
-    const T phi = S.b2 * (S.hq2 * w[0] - uw + w[E]);
-    const T psi = (nw - S.un * w[0]) * S.ic;
-    a[0] = T(0.5) * (phi - psi);
-    a[1] = w[0] - phi;
+    const T phi = S.pB * (S.hq2 * w[0] - uw + w[E]);
+    const T psi = (nw - S.un * w[0]) * S.pI;
+    a[0] = phi - psi;
+    a[1] = w[0] - T(2) * phi;
     a[2] = t1w - S.ut1 * w[0];
     if constexpr (DIM == 3) a[3] = t2w - S.ut2 * w[0];
-    a[E] = T(0.5) * (phi + psi);
+    a[E] = phi + psi;
 }
 
 // R h: back to conservative components
@@ -494,7 +514,7 @@ __device__ __forceinline__ void face_flux_weno(const LD& ld, const SchemeK& sk,
     // per stencil node: projections of dF~ (a) and dQ~ (b) on every field
     T a[NV][6], b[NV][6];
     T mxm = T(0), mx0 = T(0), mxp = T(0);
-    double chain = double(S.ic);
+    double chain = double(S.pI);
 #pragma unroll
     for (int r = 1; r <= 6; ++r) {
         NodeDiff<DIM, T> N;
@@ -523,27 +543,31 @@ __device__ __forceinline__ void face_flux_weno(const LD& ld, const SchemeK& sk,
     for (int v = 1; v < E; ++v) lam[v] = l1;
     lam[E] = fmax(S.sigma * mxp, T(sk.glf[2]));
     // WENOCU6's eps may be far below the FP32 normal range (1e-40 in the
-    // published scheme): the FP32 path floors it at 1e-30
+    // published scheme): the FP32 path floors it at 1e-30.  The
+    // reconstructions take twice the split values a +- lambda b (the split's
+    // 1/2 goes on the back-projected sum), so WENOCU6 takes 4 eps and WENO5,
+    // whose indicators are also scaled by 4, 16 eps.
     const T eps = (CU6 && sizeof(T) == 4) ? fmax(T(sk.eps), T(1e-30)) : T(sk.eps);
+    const T epsw = CU6 ? T(4) * eps : T(16) * eps;
     T h[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         T vp[6], vm[6];
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
-            vp[r] = T(0.5) * (a[v][r] + lam[v] * b[v][r]);
-            vm[r] = T(0.5) * (a[v][5 - r] - lam[v] * b[v][5 - r]);
+            vp[r] = a[v][r] + lam[v] * b[v][r];
+            vm[r] = a[v][5 - r] - lam[v] * b[v][5 - r];
         }
         if constexpr (CU6)
-            h[v] = wenocu6<T>(vp, eps) + wenocu6<T>(vm, eps);
+            h[v] = wenocu6<T>(vp, epsw) + wenocu6<T>(vm, epsw);
         else
-            h[v] = weno5(vp[0], vp[1], vp[2], vp[3], vp[4], eps) +
-                   weno5(vm[0], vm[1], vm[2], vm[3], vm[4], eps);
+            h[v] = weno5(vp[0], vp[1], vp[2], vp[3], vp[4], epsw) +
+                   weno5(vm[0], vm[1], vm[2], vm[3], vm[4], epsw);
     }
     T o[NV];
     backproject<DIM, T>(S, h, o);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fo[v] = R.Fts[v] + double(o[v]);
+    for (int v = 0; v < NV; ++v) Fo[v] = fma(0.5, double(o[v]), R.Fts[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,7 +584,7 @@ __device__ __forceinline__ void face_flux_weno7(const LD& ld, const SchemeK& sk,
     roe<DIM, T>(ld.after(R.Vf), sk, R, S);
     T a[NV][8], b[NV][8];
     T mxm = T(0), mx0 = T(0), mxp = T(0);
-    double chain = double(S.ic);
+    double chain = double(S.pI);
 #pragma unroll
     for (int r = 0; r <= 7; ++r) {
         NodeDiff<DIM, T> N;
@@ -587,22 +611,23 @@ __device__ __forceinline__ void face_flux_weno7(const LD& ld, const SchemeK& sk,
 #pragma unroll
     for (int v = 1; v < E; ++v) lam[v] = l1;
     lam[E] = fmax(S.sigma * mxp, T(sk.glf[2]));
-    const T eps = T(sk.eps);
+    // twice the split values, 4 eps; the split's 1/2 on the back-projected sum
+    const T eps4 = T(4) * T(sk.eps);
     T h[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         T vp[7], vm[7];
 #pragma unroll
         for (int r = 0; r < 7; ++r) {
-            vp[r] = T(0.5) * (a[v][r] + lam[v] * b[v][r]);
-            vm[r] = T(0.5) * (a[v][7 - r] - lam[v] * b[v][7 - r]);
+            vp[r] = a[v][r] + lam[v] * b[v][r];
+            vm[r] = a[v][7 - r] - lam[v] * b[v][7 - r];
         }
-        h[v] = weno7<T>(vp, eps) + weno7<T>(vm, eps);
+        h[v] = weno7<T>(vp, eps4) + weno7<T>(vm, eps4);
     }
     T o[NV];
     backproject<DIM, T>(S, h, o);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fo[v] = R.Fts[v] + double(o[v]);
+    for (int v = 0; v < NV; ++v) Fo[v] = fma(0.5, double(o[v]), R.Fts[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -628,7 +653,7 @@ __device__ __forceinline__ void face_flux_lu5(const LD& ld, const SchemeK& sk,
 #pragma unroll
     for (int v = 0; v < NV; ++v) cen[v] = del[v] = 0.0;
     T mxm = T(0), mx0 = T(0), mxp = T(0);
-    double chain = double(S.ic);
+    double chain = double(S.pI);
 #pragma unroll
     for (int r = 1; r <= 6; ++r) {
         NodeDiff<DIM, T> N;

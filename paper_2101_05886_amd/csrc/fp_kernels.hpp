@@ -68,6 +68,36 @@ typedef __attribute__((address_space(1))) double gdouble;
 __device__ __forceinline__ gdouble* gmem(double* p) { return (gdouble*)p; }
 __device__ __forceinline__ const gdouble* gmem(const double* p) { return (const gdouble*)p; }
 
+// Buffer access to one variable array: the resource (base, size) is
+// wave-uniform and lives in scalar registers, every lane supplies a 32-bit
+// byte offset, so no 64-bit vector address arithmetic is spent per access.
+// Reads past `elems` return 0 by the hardware's range check.  A variable array must stay below 4 GiB (checked
+// by the host: at most 2^29 nodes per block, ghosts included).
+#define FP_BUF_FLAGS 0x00020000
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const double* base, long elems) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(elems * 8), FP_BUF_FLAGS);
+}
+__device__ __forceinline__ double ldb(const double* base, long elems, unsigned byteoff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(buf(base, elems), byteoff, 0, 0));
+}
+// A wave-uniform pointer the compiler must treat as redefined at this point,
+// so that what derives from it (the per-variable buffer resources) is
+// rebuilt at the use from a few scalar operations instead of being hoisted
+// into long-lived scalar registers, which would spill into vector lanes.
+__device__ __forceinline__ const double* rebase(const double* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+__device__ __forceinline__ double* rebase(double* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+typedef unsigned int u32x2_t __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+__device__ __forceinline__ void stb(double* base, long elems, unsigned byteoff, double x) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, x), buf(base, elems), byteoff, 0, 0);
+}
+
 // The epilogue split in two, so that its loads can be issued early (before
 // the face computation) and its stores done late: epi_load reads what the
 // mode needs at node `off`, epi_store applies the same arithmetic as
@@ -79,22 +109,28 @@ struct EpiPre {
 
 // (own_qv: the caller supplies 1/J and the stage input itself, from values
 // it has staged already)
+// (buffer loads and stores: one 32-bit byte offset per lane serves every
+// variable array, whose base goes into the wave-uniform resource)
 template <int NV>
 __device__ __forceinline__ void epi_load(const EpiK& ep, long vol, long off, EpiPre<NV>& p,
                                          bool own_qv = false) {
     if (ep.mode == EPI_FIRST) return;
+    const unsigned bo = (unsigned)off * 8u;
+    const double* R = rebase(ep.R);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) p.R[v] = gmem(ep.R)[v * vol + off];
+    for (int v = 0; v < NV; ++v) p.R[v] = ldb(R + v * vol, vol, bo);
     if (ep.mode == EPI_MID) return;
-    if (!own_qv) p.V = gmem(ep.metV)[off];
+    if (!own_qv) p.V = ldb(rebase(ep.metV), vol, bo);
     if (ep.mode == EPI_LAST_RES) return;
     if (!own_qv) {
+        const double* qin = rebase(ep.qin);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) p.qin[v] = gmem(ep.qin)[v * vol + off];
+        for (int v = 0; v < NV; ++v) p.qin[v] = ldb(qin + v * vol, vol, bo);
     }
     if (ep.stage0) return;
+    const double* qn = rebase(ep.qn);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) p.qn[v] = gmem(ep.qn)[v * vol + off];
+    for (int v = 0; v < NV; ++v) p.qn[v] = ldb(qn + v * vol, vol, bo);
 }
 
 // The same epilogue with its mode fixed to MID (for a sweep that is never
@@ -108,38 +144,30 @@ __device__ __forceinline__ EpiK epi_mid(const EpiK& ep) {
 template <int NV>
 __device__ __forceinline__ void epi_store(const EpiK& ep, long vol, long off, const EpiPre<NV>& p,
                                           const double (&d)[NV]) {
+    const unsigned bo = (unsigned)off * 8u;
     if (ep.mode == EPI_FIRST) {
+        double* R = rebase(ep.R);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gmem(ep.R)[v * vol + off] = -d[v];
+        for (int v = 0; v < NV; ++v) stb(R + v * vol, vol, bo, -d[v]);
     } else if (ep.mode == EPI_MID) {
+        double* R = rebase(ep.R);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gmem(ep.R)[v * vol + off] = p.R[v] - d[v];
+        for (int v = 0; v < NV; ++v) stb(R + v * vol, vol, bo, p.R[v] - d[v]);
     } else if (ep.mode == EPI_LAST_RES) {
         const double J = 1.0 / p.V;  // one division per node, not one per variable
+        double* out = rebase(ep.out);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) gmem(ep.out)[v * vol + off] = (p.R[v] - d[v]) * J;
+        for (int v = 0; v < NV; ++v) stb(out + v * vol, vol, bo, (p.R[v] - d[v]) * J);
     } else {
         const double J = 1.0 / p.V;
+        double* out = rebase(ep.out);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double k = (p.R[v] - d[v]) * J;
             const double u = p.qin[v] + ep.dt * k;
-            gmem(ep.out)[v * vol + off] = ep.stage0 ? u : ep.a * p.qn[v] + ep.b * u;
+            stb(out + v * vol, vol, bo, ep.stage0 ? u : ep.a * p.qn[v] + ep.b * u);
         }
     }
-}
-
-// Buffer access to one variable array: the resource (base, size) is
-// wave-uniform and lives in scalar registers, every lane supplies a 32-bit
-// byte offset, so no 64-bit vector address arithmetic is spent per access.
-// Reads past `elems` return 0 by the hardware's range check.  A variable array must stay below 4 GiB (checked
-// by the host: at most 2^29 nodes per block, ghosts included).
-#define FP_BUF_FLAGS 0x00020000
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf(const double* base, long elems) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(elems * 8), FP_BUF_FLAGS);
-}
-__device__ __forceinline__ double ldb(const double* base, long elems, unsigned byteoff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(buf(base, elems), byteoff, 0, 0));
 }
 
 // Reads the stencil of face i+1/2 of one grid line along axis DIR: slot r
@@ -192,12 +220,14 @@ struct LineLoader {
 template <int PREC>
 using char_t = typename std::conditional<PREC == 1, float, double>::type;
 
-// One dword per lane from a variable array into LDS (global-to-LDS DMA: no
-// registers hold the data; completion is tracked by the wave's vmcnt).
-// Lane l writes the dword at lds + 4 l.
-__device__ __forceinline__ void dma_dword(const double* var, void* lds, unsigned byteoff) {
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const char*>(var) + byteoff,
-                                     (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+// One dword per lane from a variable array of `elems` doubles into LDS
+// (buffer-to-LDS DMA: no registers hold the data; completion is tracked by
+// the wave's vmcnt).  Lane l writes the dword at lds + 4 l.  The array's
+// base goes into the wave-uniform resource, so the lane supplies only its
+// 32-bit byte offset (no per-load 64-bit address arithmetic).
+__device__ __forceinline__ void dma_dword(const double* var, long elems, void* lds, unsigned byteoff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(buf(var, elems), (__attribute__((address_space(3))) void*)lds, 4,
+                                             byteoff, 0, 0, 0);
 }
 
 // The wave's index in its workgroup, as a value the compiler knows to be
@@ -319,11 +349,13 @@ __device__ __forceinline__ void x_stage(const GeoK& G, const double* __restrict_
         const unsigned lb = (unsigned)G.base + l1 * (unsigned)G.sd[1] + l2 * (unsigned)G.sd[2];
         const unsigned oq = (lb + (unsigned)xq) * 8u + (lane & 1) * 4u;
         const unsigned om = (lb + (unsigned)xm) * 8u + (lane & 1) * 4u;
+        const double* qp = rebase(qs);
+        const double* mp = rebase(met);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) dma_dword(qs + v * G.vol, &buf[v][32 * p], oq);
-        dma_dword(met + (NMET - 1) * G.vol, &buf[NV][32 * p], om);
+        for (int v = 0; v < NV; ++v) dma_dword(qp + v * G.vol, G.vol, &buf[v][32 * p], oq);
+        dma_dword(mp + (NMET - 1) * G.vol, G.vol, &buf[NV][32 * p], om);
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) dma_dword(met + c * G.vol, &buf[NV + 1 + c][32 * p], om);
+        for (int c = 0; c < DIM; ++c) dma_dword(mp + c * G.vol, G.vol, &buf[NV + 1 + c][32 * p], om);
     }
 }
 
@@ -394,8 +426,9 @@ __device__ __forceinline__ void x_compute(const GeoK& G, const SchemeK& sk, cons
         if (ACC) {
             epi_store<NV>(epi_mid(ep), G.vol, noff, pre, d);
         } else {
+            double* R = rebase(ep.R);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) gmem(ep.R)[v * G.vol + noff] = -d[v];
+            for (int v = 0; v < NV; ++v) stb(R + v * G.vol, G.vol, (unsigned)noff * 8u, -d[v]);
         }
     }
 }
@@ -537,12 +570,14 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
         const unsigned qo = (unsigned)(tt * sdD) * 8u, mo = (unsigned)(t * sdD) * 8u;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
+            const double* qp = rebase(qs);
+            const double* mp = rebase(met);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) dma_dword(qs + v * vol, &L.ring[slot][v][32 * h], loff[h] + qo);
-            dma_dword(met + (NMET - 1) * vol, &L.ring[slot][NV][32 * h], loff[h] + mo);
+            for (int v = 0; v < NV; ++v) dma_dword(qp + v * vol, vol, &L.ring[slot][v][32 * h], loff[h] + qo);
+            dma_dword(mp + (NMET - 1) * vol, vol, &L.ring[slot][NV][32 * h], loff[h] + mo);
 #pragma unroll
             for (int c = 0; c < DIM; ++c)
-                dma_dword(met + (DIR * DIM + c) * vol, &L.ring[slot][NV + 1 + c][32 * h], loff[h] + mo);
+                dma_dword(mp + (DIR * DIM + c) * vol, vol, &L.ring[slot][NV + 1 + c][32 * h], loff[h] + mo);
         }
     };
     for (int r = w; r < W::WIN; r += 4) load_row(tb + r);
