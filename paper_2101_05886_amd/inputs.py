@@ -146,11 +146,28 @@ def paper_wavy_grid_2d(n: int, g: int, Y: int, L: float = 20.0, A: float = 0.6,
     return np.ascontiguousarray(np.stack([x, y]))
 
 
+def paper_random_displacement(shape, frac: float, rng) -> np.ndarray:
+    """The paper's random grid displacement (the law its Sec. 4.2.2 prints for
+    the cylinder grid: xi = i + frac*phi, eta = j + frac*sqrt(1 - phi^2),
+    phi ~ U(0, 1)): a displacement of ``frac`` node spacings in a random
+    direction of the first quadrant, in index units; shape (2, *shape)."""
+    phi = rng.uniform(0.0, 1.0, size=shape)
+    return frac * np.stack([phi, np.sqrt(1.0 - phi * phi)])
+
+
 def random_grid_2d(n: int, g: int, Y: int, L: float = 20.0, frac: float = 0.2,
                    seed: int = 0) -> np.ndarray:
-    """Cartesian grid with every unique node moved by ``frac`` of the spacing
-    in a random direction (the random grid of Sec. 4.1.1)."""
-    return wavy_grid(2, n, L, g, Y, amp=0.0, jitter=frac, seed=seed)
+    """Periodic Cartesian grid on [-L/2, L/2)^2 with every unique node moved
+    by ``frac`` of the spacing in a random direction (the random grid of
+    Sec. 4.1.1, with the displacement law of paper_random_displacement);
+    ghost nodes are the periodic images shifted by the period."""
+    gc = coord_ghost(g, Y)
+    h = L / n
+    ax = -L / 2 + np.arange(-gc, n + gc) * h
+    eta, xi = np.meshgrid(ax, ax, indexing="ij")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = paper_random_displacement((n, n), frac, rng) * h
+    return np.ascontiguousarray(np.stack([xi, eta]) + _periodic_take(d, 2, [n, n], gc))
 
 
 def cartesian_grid(ndim: int, n, g: int, Y: int, spacing=1.0, origin=0.0) -> np.ndarray:
@@ -345,10 +362,11 @@ def dmr_grid(nx: int = 961, ny: int = 241, rand: float = 0.05, g: int = 3, Y: in
              Lx: float = 4.0, Ly: float = 1.0) -> np.ndarray:
     """Grid of the double Mach reflection on [0, Lx] x [0, Ly] with nx x ny
     nodes, every node moved by ``rand`` of the spacing in a random direction
-    (as the random grid of Sec. 4.1.1); nodes on the boundary lines keep the
-    component along the line only and the corners stay.  Ghost layers: the
-    mirror image of the interior about the bottom wall y = 0, point
-    reflections through the boundary nodes on the other sides."""
+    (the displacement law of paper_random_displacement, as the random grid of
+    Sec. 4.1.1); nodes on the boundary lines keep the component along the
+    line only and the corners stay.  Ghost layers: the mirror image of the
+    interior about the bottom wall y = 0, point reflections through the
+    boundary nodes on the other sides."""
     gc = coord_ghost(g, Y)
     assert nx > gc and ny > gc
     hx, hy = Lx / (nx - 1), Ly / (ny - 1)
@@ -356,9 +374,9 @@ def dmr_grid(nx: int = 961, ny: int = 241, rand: float = 0.05, g: int = 3, Y: in
     j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     x = i * hx
     y = j * hy
-    ang = rng.uniform(0.0, 2.0 * math.pi, x.shape)
-    dx = rand * hx * np.cos(ang)
-    dy = rand * hy * np.sin(ang)
+    d = paper_random_displacement(x.shape, rand, rng)
+    dx = hx * d[0]
+    dy = hy * d[1]
     inner_i = (i > 0) & (i < nx - 1)
     inner_j = (j > 0) & (j < ny - 1)
     x = x + np.where(inner_i, dx, 0.0)

@@ -53,10 +53,15 @@ def test_table1_free_stream_preserving_at_round_off(grid, Y):
     assert l2 < 10 * paper["L2"] and li < 10 * paper["Linf"]
 
 
-def test_table1_random_standard_fails_visibly():
+def test_table1_random_standard_weno5():
+    # the random grid with the paper's displacement law (the one it prints
+    # for the cylinder grid): the standard scheme's errors within 2x of
+    # Table 1 (ours 1.80e-2 / 5.97e-2 against 1.29e-2 / 4.41e-2; a uniformly
+    # random direction gives 5.6e-2 / 2.1e-1, four to five times the paper)
     paper = GOLD["table1"]["random"]["WENO5"]
-    l2, _ = run_table1("random", O.Scheme("weno5", 6, False), 6)
-    assert l2 > 0.1 * paper["L2"]
+    l2, li = run_table1("random", O.Scheme("weno5", 6, False), 6)
+    assert 0.5 < l2 / paper["L2"] < 2.0
+    assert 0.5 < li / paper["Linf"] < 2.0
 
 
 def run_vortex(recon, Y, n):
