@@ -15,10 +15,14 @@ workloads: --workload c1/c2/c3/c3m/c3w7/c3cu6 and c3v (Navier-Stokes); linked
 blocks: c3x8; the double Mach reflection with its boundary faces: dmr; the
 serving stream alone: --workload c5.
 
-Prints ONE JSON line.  Extra fields: the per-kernel roofline of the dominant
-sweep kernel (timed with HIP events on the stream it runs on), the
-stage-level HBM figure of the method's compulsory traffic, and the FP64 CPU
-oracle timed on the host on a bounded sample of the same workload.
+Prints ONE JSON line.  Extra fields: the roofline of the dominant sweep
+kernel (timed with HIP events on the stream it runs on): the method's
+algorithmic flops per face over the launch time against the 78.6 TFLOP/s
+vector-ALU ceiling, with the VALU issue rate and the algorithmic HBM rate of
+the same launch beside it; the stage-level HBM figure of the method's
+compulsory traffic; the median of repeated timed regions; the serving stream
+at 0.5x, 0.8x and 1.1x load; and the FP64 CPU oracle timed on the host on a
+bounded sample of the same workload, with all threads and with one.
 """
 from __future__ import annotations
 
@@ -38,6 +42,14 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+# The ALU ceiling this build can reach, from the chip's unit counts: 256 CUs
+# x 4 SIMDs x 16 lanes x 2 flop (fma) x 2.4 GHz = 78.6 TFLOP/s for FP64 and
+# for non-packed FP32 alike (the published 157.3 TFLOP/s FP32 needs packed
+# FP32 instructions, which this build disables).
+CU, SIMD_PER_CU, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
+PEAK_ALU_TFLOPS = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ / 1e12
+# VALU issue: one wave64 instruction occupies a SIMD for 4 cycles
+VALU_ISSUE_PER_S = CU * SIMD_PER_CU * CLOCK_HZ / 4.0
 
 # Compulsory HBM bytes per cell-stage of the method (read the stage input,
 # Q^n in stages 2-3, the metrics, write the stage output; FP64 storage):
@@ -53,6 +65,34 @@ FLOPS_FILE = os.path.join(ROOT, "profiles", "flops_per_face.json")
 # HBM bytes per launch of the sweep kernels from FETCH_SIZE / WRITE_SIZE
 # counter runs scaled by a plain copy kernel: profiles/hbm_traffic.json.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+# VALU wave instructions per launch (SQ_INSTS_VALU) of the sweep kernels:
+# profiles/valu_insts.json.
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_insts.json")
+
+
+def alg_flops_per_face(recon, ndim, Y):
+    """Floating-point operations of one face flux of the method (add, mul,
+    div, sqrt = 1, fma = 2), counted step by step from the algorithm, not
+    from a kernel: the face reference state (interpolation of 1/J, s and
+    Q/J of order Y, Q*, F(Q*).s), per stencil node the reference-subtracted
+    dQ~ and dF~, the Roe average and eigen-structure with the local speeds,
+    two characteristic projections per node (structured Euler form), the
+    split a +- lambda b, the reconstructions, the back-projection, add-back
+    and the flux difference.  3D WENO5-JS with sixth-order metrics: 1,897."""
+    D = ndim
+    nv = D + 2
+    S = 8 if recon == "weno7" else 6  # stencil nodes
+    ref = 2 * Y * (1 + D) + 3 * Y * nv + nv + 8 * D + 6
+    node = (2 * nv + 12 * D + 10) * S
+    tang = 29 if D == 3 else 3
+    eig = (11 * D + 20) + (3 * D + 2) + (2 * D - 1) + tang + (2 * D + 9) * S + 3
+    proj = 2 * (2 * D - 1) + (D - 1) * (2 * D - 1) + 4 + 3 + 2 + 1 + 2 * (D - 1) + 2
+    back = 35 if D == 3 else 24
+    if recon == "linup5":
+        recon_f = nv * 22 + proj + nv + 2 * nv
+        return ref + node + eig + recon_f + back + nv + nv
+    per = {"weno5": 60, "weno7": 150, "wenocu6": 155}[recon]
+    return ref + node + eig + 2 * S * proj + 4 * nv * S + 2 * nv * per + back + nv + nv
 
 
 def csrc_hash():
@@ -75,6 +115,67 @@ def counter_table(path):
     except (OSError, ValueError):
         return {}, False
     return table, table.get("csrc_sha256") == csrc_hash()
+
+def faces_along(n, d):
+    """faces of every line along axis d of a block of interior extents n"""
+    f = n[d] + 1
+    for e, m in enumerate(n):
+        if e != d:
+            f *= m
+    return f
+
+
+def roofline(recon, ndim, Y, prec, kernel, kernel_ms, faces, nodes, key):
+    """Roofline of one sweep launch.  Bound: the vector ALU.  `achieved` is
+    the method's algorithmic flops (alg_flops_per_face x the faces the
+    launch evaluates) over the launch's duration, against the 78.6 TFLOP/s
+    ALU ceiling.  Beside it: the VALU issue rate (SQ_INSTS_VALU of the same
+    launch from profiles/valu_insts.json, 4 cycles per wave instruction, over
+    the issue capacity of 1,024 SIMDs at 2.4 GHz), the algorithmic HBM rate
+    (the method's compulsory bytes per cell-stage split over the stage's
+    ndim sweeps), and the measured HBM bytes of the launch (FETCH_SIZE +
+    WRITE_SIZE, calibrated, profiles/hbm_traffic.json).  Counter tables
+    taken on other kernel sources are reported as null."""
+    fpf = alg_flops_per_face(recon, ndim, Y)
+    t = kernel_ms * 1e-3
+    achieved = fpf * faces / t / 1e12
+    ttab, tcur = counter_table(TRAFFIC_FILE)
+    vtab, vcur = counter_table(VALU_FILE)
+    ftab, fcur = counter_table(FLOPS_FILE)
+    traffic = ttab.get(key) if tcur else None
+    insts = vtab.get(key) if vcur else None
+    counted = ftab.get(f"{recon}/{ndim}d/{prec}/m{Y}") if fcur else None
+    alg_bytes = STAGE_BYTES[ndim] / ndim * nodes
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_ALU_TFLOPS, "traffic": traffic,
+            "peak_basis": "256 CUs x 4 SIMDs x 16 lanes x 2 flop (fma) x 2.4 GHz: FP64 and non-packed FP32",
+            "kernel": kernel, "kernel_ms": kernel_ms, "faces_per_launch": faces,
+            "alg_flops_per_face": fpf, "counters_current": bool(tcur and vcur),
+            "valu_issue": ({"insts_per_launch": insts, "insts_per_face": insts * 64.0 / faces,
+                            "frac": insts / (VALU_ISSUE_PER_S * t)} if insts else None),
+            "hbm_alg": {"bytes_per_launch": alg_bytes, "achieved_gbs": alg_bytes / t / 1e9,
+                        "peak_gbs": PEAK_HBM_GBS, "frac": alg_bytes / t / 1e9 / PEAK_HBM_GBS},
+            "traffic_gbs": traffic / t / 1e9 if traffic else None,
+            "traffic_bytes_per_node": traffic / nodes if traffic else None,
+            "counted_flops_per_face": counted}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def median_rate(times_ms, work):
+    """median, min and max of work / time over repeated timed regions"""
+    rates = sorted(work / (t * 1e-3) for t in times_ms)
+    return {"n": len(rates), "median": rates[len(rates) // 2], "min": rates[0], "max": rates[-1]}
+
 
 WORKLOADS = {
     "c2": dict(name="3D isentropic vortex (strength 5, radius 1), 128^3 periodic wavy grid "
@@ -116,7 +217,7 @@ WORKLOADS = {
                     "with a vortex or O-grid with frozen ghosts; Mach U(0.3, 2.0), angle U(0, 10) deg; "
                     "200 RK3 steps each; WENO5-JS with 6th-order metrics, FP32-mixed; continuous batching",
                ndim=3, Y=6, recon="weno5", prec="mixed", requests=500, seed=5, load=0.8,
-               capacity_requests=100, slots=64, round_steps=10),
+               capacity_requests=100, slots=64, round_steps=10, other_loads=(0.5, 1.1), other_requests=300),
     "dmr": dict(name="2D double Mach reflection (Mach 10, 60 deg), 961x241 nodes on [0,4]x[0,1] with a 5% "
                      "random grid (seed 11), WENO5-JS with 6th-order metrics and global Lax-Friedrichs "
                      "splitting, FP64, boundary faces (held inflow, outflow, slip wall, exact moving shock) "
@@ -162,20 +263,33 @@ def cpu_baseline(w, xyz, q, g, budget_s=20.0):
     met = O.metrics(og, w["Y"], xyz)
     sc = O.Scheme(w["recon"], w["Y"], True, mu=w.get("mu", 0.0), prandtl=w.get("prandtl", 0.72))
     dt = O.max_dt(og, sc, met, q, w["cfl"])
-    qq = q.copy()
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        qq = O.rk3_step(og, sc, met, qq, dt)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s * 0.5 or steps >= 1000:
-            break
-    el = time.perf_counter() - t0
     nodes = w["n"] ** w["ndim"]
-    return {"value": nodes * 3 * steps / el, "unit": "cell-stage updates/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} full RK3 step(s) of the same {w['n']}^{w['ndim']} grid and state, "
-                      f"FP64 oracle (gcc -O2, OpenMP over grid lines), {el:.1f} s{note}"}
+
+    def timed(limit):
+        qq = q.copy()
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            qq = O.rk3_step(og, sc, met, qq, dt)
+            steps += 1
+            if time.perf_counter() - t0 > limit or steps >= 1000:
+                break
+        return steps, time.perf_counter() - t0
+
+    threads = O.num_threads()
+    steps, el = timed(budget_s * 0.5)
+    out = {"value": nodes * 3 * steps / el, "unit": "cell-stage updates/s", "cores": threads,
+           "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "sample": f"{steps} full RK3 step(s) of the same {w['n']}^{w['ndim']} grid and state, "
+                     f"FP64 oracle (gcc -O2, OpenMP over grid lines, {threads} threads), {el:.1f} s{note}"}
+    O.set_num_threads(1)
+    try:
+        steps1, el1 = timed(budget_s * 0.25)
+    finally:
+        O.set_num_threads(threads)
+    out["single_thread"] = {"value": nodes * 3 * steps1 / el1, "cores": 1,
+                            "sample": f"{steps1} full RK3 step(s), one thread, {el1:.1f} s"}
+    return out
 
 
 def nodes_of(w):
@@ -209,24 +323,39 @@ def cpu_baseline_blocks(w, blocks, g, budget_s=20.0):
     order) as fit in about budget_s seconds (at least one)."""
     import oracle as O
     sc = O.Scheme(w["recon"], w["Y"], True)
-    nodes = 0
-    used = 0
-    el = 0.0
-    for n, xyz, q in blocks:
-        og = O.Grid(3, n, g, bc=[1, 1, 1])
-        met = O.metrics(og, w["Y"], xyz)
-        dt = O.max_dt(og, sc, met, q, w["cfl"])
-        t0 = time.perf_counter()
-        O.rk3_step(og, sc, met, q, dt)
-        el += time.perf_counter() - t0
-        nodes += int(np.prod(n))
-        used += 1
-        if el > budget_s * 0.5:
-            break
-    return {"value": nodes * 3 / el, "unit": "cell-stage updates/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"one RK3 step of each of the first {used} of the {len(blocks)} blocks "
-                      f"({nodes} nodes), FP64 oracle (gcc -O2, OpenMP over grid lines), {el:.1f} s"}
+
+    def timed(limit):
+        nodes = used = 0
+        el = 0.0
+        for n, xyz, q in blocks:
+            og = O.Grid(3, n, g, bc=[1, 1, 1])
+            met = O.metrics(og, w["Y"], xyz)
+            dt = O.max_dt(og, sc, met, q, w["cfl"])
+            t0 = time.perf_counter()
+            O.rk3_step(og, sc, met, q, dt)
+            el += time.perf_counter() - t0
+            nodes += int(np.prod(n))
+            used += 1
+            if el > limit:
+                break
+        return nodes, used, el
+
+    threads = O.num_threads()
+    nodes, used, el = timed(budget_s * 0.5)
+    out = {"value": nodes * 3 / el, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "sample": f"one RK3 step of each of the first {used} of the {len(blocks)} blocks "
+                     f"({nodes} nodes), FP64 oracle (gcc -O2, OpenMP over grid lines, {threads} threads), "
+                     f"{el:.1f} s"}
+    O.set_num_threads(1)
+    try:
+        nodes1, used1, el1 = timed(budget_s * 0.25)
+    finally:
+        O.set_num_threads(threads)
+    out["single_thread"] = {"value": nodes1 * 3 / el1, "cores": 1,
+                            "sample": f"one RK3 step of each of the first {used1} blocks ({nodes1} nodes), "
+                                      f"one thread, {el1:.1f} s"}
+    return out
 
 
 def bench_dmr(args, w):
@@ -261,6 +390,14 @@ def bench_dmr(args, w):
     ms_total = e0.elapsed_time(e1)
     nodes_n = nx * ny
     value = nodes_n * 3 * args.steps / (ms_total * 1e-3)
+    reps = [ms_total]
+    for i in range(args.repeats - 1):
+        e0.record()
+        fp.solve_bcs(G, S, bcs, met, qg, work, t + (i + 1) * args.steps * dt, dt, args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1))
+    t += (args.repeats - 1) * args.steps * dt
     healthy = int(fp.check_state(G, S, qg).item()) == 0
     # per-launch durations of instrumented steps of the same run (boundary
     # faces, global speeds and sweeps of every stage), after the timed region
@@ -269,13 +406,12 @@ def bench_dmr(args, w):
     per_kind = profiled_kinds(fp, G, S, met, qg, work, dt, args.kernel_reps, bcs=bcs, t=t_end)
     kt = {d: per_kind[d] for d in range(2)}
     dom = max(kt, key=kt.get)
-    ftab, fcur = counter_table(FLOPS_FILE)
-    ttab, tcur = counter_table(TRAFFIC_FILE)
-    fpf = ftab.get(f"{w['recon']}/2d/fp64/m{Y}")
-    traffic = ttab.get(f"dmr/{names[dom]}") if tcur else None
     # algorithmic units of one launch: the n_d + 1 faces of every line
-    faces = (nx + 1) * ny if dom == 0 else nx * (ny + 1)
-    achieved = fpf * faces / (kt[dom] * 1e-3) / 1e12 if fpf else None
+    roof = roofline(w["recon"], 2, Y, "fp64", names[dom], kt[dom], faces_along([nx, ny], dom), nodes_n,
+                    f"dmr/{names[dom]}")
+    roof.update({"kernel_ms_by_dir": [round(kt[d], 4) for d in range(2)],
+                 "glf_ms_per_stage": per_kind.get(5), "bc_faces_ms_per_stage": per_kind.get(6),
+                 "sweeps_share_of_step": 3 * (kt[0] + kt[1]) / (ms_total / args.steps)})
     out = {
         "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_total / args.steps,
@@ -283,14 +419,8 @@ def bench_dmr(args, w):
         "data": "synthetic",
         "config": {"workload": w["name"], "nodes": nodes_n, "metric_order": Y, "recon": w["recon"],
                    "precision": "fp64", "splitting": "glf", "dt": dt},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS if achieved else None, "traffic": traffic,
-                     "kernel": names[dom], "kernel_ms": kt[dom], "flops_per_face": fpf,
-                     "counters_current": fcur,
-                     "traffic_gbs": traffic / (kt[dom] * 1e-3) / 1e9 if traffic else None,
-                     "kernel_ms_by_dir": [round(kt[d], 4) for d in range(2)],
-                     "glf_ms_per_stage": per_kind.get(5), "bc_faces_ms_per_stage": per_kind.get(6),
-                     "sweeps_share_of_step": 3 * (kt[0] + kt[1]) / (ms_total / args.steps)},
+        "roofline": roof,
+        "repeats": median_rate(reps, nodes_n * 3 * args.steps),
         "state_ok": healthy,
     }
     if not args.no_cpu_baseline:
@@ -357,6 +487,13 @@ def bench_links(args, w):
     ms = e0.elapsed_time(e1)
     nodes = n ** 3
     value = nodes * 3 * args.steps / (ms * 1e-3)
+    reps = [ms]
+    for _ in range(args.repeats - 1):
+        e0.record()
+        b.solve(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1))
     healthy = all(int(fp.check_state(e[0], sc, e[2]).item()) == 0 for e in ent)
     kinds = {}
     for _, kind, t in b.profile_step():
@@ -366,17 +503,9 @@ def bench_links(args, w):
     names = {0: "kb_sweep_x", 1: "kb_sweep_wg<eta>", 2: "kb_sweep_wg<zeta>", 3: "kb_frozen_ghosts",
              4: "kb_halo"}
     dom = max((k for k in pk if k < 3), key=pk.get)
-    ftab, fcur = counter_table(FLOPS_FILE)
-    ttab, tcur = counter_table(TRAFFIC_FILE)
-    fpf = ftab.get(f"{w['recon']}/3d/{w['prec']}/m{Y}")
-    traffic = ttab.get(f"c3x8/{names[dom]}") if tcur else None
-    achieved = fpf * nodes / (pk[dom] * 1e-3) / 1e12 if fpf else None
-    peak = PEAK_FP64_TFLOPS if w["prec"] == "fp64" else PEAK_FP32_TFLOPS
-    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak if achieved else None, "traffic": traffic,
-            "kernel": names[dom], "kernel_ms": pk[dom], "flops_per_face": fpf, "counters_current": fcur,
-            "traffic_gbs": traffic / (pk[dom] * 1e-3) / 1e9 if traffic else None,
-            "kernel_ms_by_kind": {names[k]: round(v, 4) for k, v in sorted(pk.items())}}
+    faces = len(ent) * faces_along(sizes, dom)
+    roof = roofline(w["recon"], 3, Y, w["prec"], names[dom], pk[dom], faces, nodes, f"c3x8/{names[dom]}")
+    roof["kernel_ms_by_kind"] = {names[k]: round(v, 4) for k, v in sorted(pk.items())}
     # the exchange moves g ghost layers of every linked face: NV values read
     # from the neighbour and written into the block, FP64
     halo_bytes = len(links) * g * sizes[0] * sizes[1] * 5 * 8 * 2
@@ -388,6 +517,7 @@ def bench_links(args, w):
         "config": {"workload": w["name"], "blocks": len(ent), "links": len(links), "nodes": nodes,
                    "metric_order": Y, "recon": w["recon"], "precision": w["prec"], "segment": seg, "dt": dt},
         "roofline": roof,
+        "repeats": median_rate(reps, nodes * 3 * args.steps),
         "interfaces": {"kernel": "kb_halo", "ms_per_stage": pk.get(4), "bytes_per_stage": halo_bytes,
                        "achieved_gbs": halo_bytes / (pk[4] * 1e-3) / 1e9 if pk.get(4) else None,
                        "peak_gbs": PEAK_HBM_GBS},
@@ -431,6 +561,13 @@ def bench_batch(args, w):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
+        reps = [ms]
+        for _ in range(args.repeats - 1):
+            e0.record()
+            b.solve(args.steps)
+            e1.record()
+            torch.cuda.synchronize()
+            reps.append(e0.elapsed_time(e1))
         flag_ok = True
         for G, met, qg, work, dt in ent:
             flag_ok = flag_ok and int(fp.check_state(G, sc, qg).item()) == 0
@@ -442,7 +579,7 @@ def bench_batch(args, w):
             kinds.setdefault(kind, []).append(t)
         per_kernel[prec] = {k: sum(v) / len(v) for k, v in kinds.items()}
         res[prec] = dict(value=nodes * 3 * args.steps / (ms * 1e-3), ms_step=ms / args.steps, seg=seg,
-                         ok=flag_ok)
+                         ok=flag_ok, repeats=median_rate(reps, nodes * 3 * args.steps))
         progress(f"batch {prec}: {res[prec]['value']:.3e} cell-stage/s (segment {seg})")
         b.close()
         del ent
@@ -451,17 +588,14 @@ def bench_batch(args, w):
              4: "kb_halo"}
     pk = per_kernel["mixed"]
     dom = max((k for k in pk if k < 3), key=pk.get)
-    ftab, fcur = counter_table(FLOPS_FILE)
-    ttab, tcur = counter_table(TRAFFIC_FILE)
-    fpf = ftab.get(f"{w['recon']}/3d/mixed/m{w['Y']}")
-    traffic = ttab.get(f"c4/{names[dom]}") if tcur else None
-    achieved = fpf * nodes / (pk[dom] * 1e-3) / 1e12 if fpf else None
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": traffic,
-            "kernel": names[dom], "kernel_ms": pk[dom], "flops_per_face": fpf, "counters_current": fcur,
-            "traffic_gbs": traffic / (pk[dom] * 1e-3) / 1e9 if traffic else None,
-            "kernel_ms_by_kind": {names[k]: round(v, 4) for k, v in sorted(pk.items())},
-            "kernel_ms_by_kind_fp64": {names[k]: round(v, 4) for k, v in sorted(per_kernel["fp64"].items())}}
+    faces = sum(faces_along(n, dom) for n, _, _ in blocks)
+    roof = roofline(w["recon"], 3, w["Y"], "mixed", names[dom], pk[dom], faces, nodes, f"c4/{names[dom]}")
+    roof["kernel_ms_by_kind"] = {names[k]: round(v, 4) for k, v in sorted(pk.items())}
+    pk64 = per_kernel["fp64"]
+    dom64 = max((k for k in pk64 if k < 3), key=pk64.get)
+    roof64 = roofline(w["recon"], 3, w["Y"], "fp64", names[dom64], pk64[dom64],
+                      sum(faces_along(n, dom64) for n, _, _ in blocks), nodes, f"c4fp64/{names[dom64]}")
+    roof64["kernel_ms_by_kind"] = {names[k]: round(v, 4) for k, v in sorted(pk64.items())}
     value = res["mixed"]["value"]
     stage_gbs = STAGE_BYTES[3] * value / 1e9
     out = {
@@ -472,8 +606,9 @@ def bench_batch(args, w):
         "config": {"workload": w["name"], "blocks": len(blocks), "nodes": nodes, "metric_order": w["Y"],
                    "recon": w["recon"], "precision": "mixed", "segment": res["mixed"]["seg"]},
         "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_step"],
-                 "segment": res["fp64"]["seg"]},
+                 "segment": res["fp64"]["seg"], "repeats": res["fp64"]["repeats"], "roofline": roof64},
         "mixed_over_fp64": value / res["fp64"]["value"],
+        "repeats": res["mixed"]["repeats"],
         "roofline": roof,
         "hbm_stage": {"bytes_per_cell_stage": STAGE_BYTES[3], "achieved": stage_gbs,
                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS},
@@ -519,6 +654,19 @@ def serve_measure(w):
     st = run(S.make_requests(w["requests"], seed=w["seed"], rate=rate))
     s = st.summary()
     progress(f"serving: {s['requests']} requests, p50 {s['p50_latency_s']:.2f} s, p99 {s['p99_latency_s']:.2f} s")
+    # the same stream (its first requests) at lighter and heavier load
+    loads = []
+    for load in sorted(set(w.get("other_loads", ())) | {w["load"]}):
+        if load == w["load"]:
+            o, count = s, w["requests"]
+        else:
+            count = w["other_requests"]
+            o = run(S.make_requests(count, seed=w["seed"], rate=load * cap)).summary()
+            progress(f"serving at {load}x: p50 {o['p50_latency_s']:.2f} s, p99 {o['p99_latency_s']:.2f} s")
+        loads.append({"load": load, "requests": count, "arrival_rate_per_s": load * cap,
+                      "p50_latency_s": o["p50_latency_s"], "p99_latency_s": o["p99_latency_s"],
+                      "mean_queue_wait_s": o["mean_queue_wait_s"], "requests_per_s": o["requests_per_s"],
+                      "cell_stage_per_s": o["cell_stage_per_s"], "peak_active": o["peak_active"]})
     return {"workload": w["name"], "requests": w["requests"], "slots": w["slots"],
             "round_steps": w["round_steps"], "hbm_budget_bytes": budget,
             "cell_stage_per_s": s["cell_stage_per_s"],
@@ -527,7 +675,7 @@ def serve_measure(w):
             "arrival_rate_per_s": rate, "closed_loop_capacity_per_s": cap,
             "closed_loop_cell_stage_per_s": closed.summary()["cell_stage_per_s"],
             "makespan_s": s["makespan_s"], "rounds": s["rounds"], "peak_active": s["peak_active"],
-            "peak_bytes": s["peak_bytes"]}
+            "peak_bytes": s["peak_bytes"], "by_load": loads}
 
 
 def bench_serve(args, w):
@@ -568,6 +716,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="batched workload only: skip the serving stream reported beside it")
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed regions of --steps steps: the first gives `value`, all of them the "
+                         "median in `repeats`")
     ap.add_argument("--n", type=int, default=None,
                     help="single-block workloads only: nodes per axis instead of the workload's own "
                          "(a size sweep; the workload's configuration is the default)")
@@ -637,6 +788,13 @@ def main():
     ms_step = ms_total / args.steps
     nodes = n ** ndim
     value = nodes * 3 * args.steps / (ms_total * 1e-3)
+    reps = [ms_total]
+    for _ in range(args.repeats - 1):
+        e0.record()
+        run(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        reps.append(e0.elapsed_time(e1))
 
     # state sanity after the timed steps
     flag = fp.check_state(G, S, qg)
@@ -663,23 +821,10 @@ def main():
         viscous = {"kernels": "k_visc_flux3 + k_visc_div3" if ndim == 3 else "k_visc_flux + k_visc_div",
                    "ms_per_stage": vms, "fluxes_ms": per_kind[7], "divergence_ms": per_kind[8], "bytes_per_node": vb,
                    "achieved_gbs": vb * nodes_of(w) / (vms * 1e-3) / 1e9, "peak_gbs": PEAK_HBM_GBS}
-    ftab, fcur = counter_table(FLOPS_FILE)
-    ttab, tcur = counter_table(TRAFFIC_FILE)
-    fpf = ftab.get(f"{w['recon']}/{ndim}d/{w['prec']}/m{Y}")
-    traffic = ttab.get(f"{args.workload}/{names[dom]}") if tcur else None
-    peak = PEAK_FP64_TFLOPS if w["prec"] == "fp64" else PEAK_FP32_TFLOPS
-    # algorithmic units of one launch: one face per node (periodic lines)
-    if fpf:
-        achieved = fpf * nodes / (kt[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": traffic}
-    else:
-        roof = {"bound": "alu", "achieved": None, "peak": peak, "unit": "TFLOP/s", "frac": None,
-                "traffic": traffic}
-    roof.update({"kernel": names[dom], "kernel_ms": kt[dom], "flops_per_face": fpf,
-                 "counters_current": fcur,
-                 "traffic_gbs": traffic / (kt[dom] * 1e-3) / 1e9 if traffic else None,
-                 "kernel_ms_by_dir": [round(kt[d], 4) for d in range(ndim)]})
+    # algorithmic units of one launch: the n + 1 faces of every line
+    roof = roofline(w["recon"], ndim, Y, w["prec"], names[dom], kt[dom], faces_along([n] * ndim, dom), nodes,
+                    f"{args.workload}/{names[dom]}")
+    roof["kernel_ms_by_dir"] = [round(kt[d], 4) for d in range(ndim)]
     stage_gbs = STAGE_BYTES[ndim] * value / 1e9
     out = {
         "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
@@ -690,6 +835,7 @@ def main():
         "config": {"workload": w["name"], "nodes": nodes, "metric_order": Y,
                    "recon": w["recon"], "precision": w["prec"], "dt": dt},
         "roofline": roof,
+        "repeats": median_rate(reps, nodes * 3 * args.steps),
         "hbm_stage": {"bytes_per_cell_stage": STAGE_BYTES[ndim], "achieved": stage_gbs,
                       "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS},
         "wall_s": wall, "state_ok": healthy,
