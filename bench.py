@@ -477,6 +477,7 @@ def bench_links(args, w):
     b.set([tuple(e) for e in ent])
     b.set_links(links)
     seg = b.autotune()
+    tiles = b.tiles()
     b.solve(max(args.warmup, 1))
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -515,7 +516,8 @@ def bench_links(args, w):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if w["prec"] == "fp64" else "f64 state, f32 reconstruction", "data": "synthetic",
         "config": {"workload": w["name"], "blocks": len(ent), "links": len(links), "nodes": nodes,
-                   "metric_order": Y, "recon": w["recon"], "precision": w["prec"], "segment": seg, "dt": dt},
+                   "metric_order": Y, "recon": w["recon"], "precision": w["prec"], "segment": seg, "tiles": tiles,
+                   "dt": dt},
         "roofline": roof,
         "repeats": median_rate(reps, nodes * 3 * args.steps),
         "interfaces": {"kernel": "kb_halo", "ms_per_stage": pk.get(4), "bytes_per_stage": halo_bytes,
@@ -553,6 +555,7 @@ def bench_batch(args, w):
         b = fp.Batch(sc, len(ent))
         b.set(ent)
         seg = b.autotune()
+        tiles = b.tiles()
         b.solve(max(args.warmup, 1))
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -579,7 +582,7 @@ def bench_batch(args, w):
             kinds.setdefault(kind, []).append(t)
         per_kernel[prec] = {k: sum(v) / len(v) for k, v in kinds.items()}
         res[prec] = dict(value=nodes * 3 * args.steps / (ms * 1e-3), ms_step=ms / args.steps, seg=seg,
-                         ok=flag_ok, repeats=median_rate(reps, nodes * 3 * args.steps))
+                         ok=flag_ok, repeats=median_rate(reps, nodes * 3 * args.steps), tiles=tiles)
         progress(f"batch {prec}: {res[prec]['value']:.3e} cell-stage/s (segment {seg})")
         b.close()
         del ent
@@ -604,9 +607,11 @@ def bench_batch(args, w):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 state, f32 reconstruction", "data": "synthetic",
         "config": {"workload": w["name"], "blocks": len(blocks), "nodes": nodes, "metric_order": w["Y"],
-                   "recon": w["recon"], "precision": "mixed", "segment": res["mixed"]["seg"]},
+                   "recon": w["recon"], "precision": "mixed", "segment": res["mixed"]["seg"],
+                   "tiles": res["mixed"]["tiles"]},
         "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_step"],
-                 "segment": res["fp64"]["seg"], "repeats": res["fp64"]["repeats"], "roofline": roof64},
+                 "segment": res["fp64"]["seg"], "tiles": res["fp64"]["tiles"], "repeats": res["fp64"]["repeats"],
+                 "roofline": roof64},
         "mixed_over_fp64": value / res["fp64"]["value"],
         "repeats": res["mixed"]["repeats"],
         "roofline": roof,

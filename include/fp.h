@@ -375,12 +375,23 @@ typedef struct {
  * Validation as described above; on an error nothing changes. */
 fp_status fp_batch_set_links(fp_batch *batch, const fp_link *links, int32_t nlinks, void *stream);
 
-/* Chooses the eta/zeta segment length of the batch's work list by timing
- * the sweeps of RK stage 1 for a set of candidates on the current blocks
- * (synchronises the stream; the blocks' workspaces are overwritten, q is
- * not).  The choice is kept for later fp_batch_set calls and written to
- * *segment if non-NULL. */
+/* Chooses the eta and zeta segment lengths of the batch's work lists (the
+ * nodes along the sweep direction one workgroup item covers) by timing RK
+ * stage 1 on the current blocks for a set of candidate targets, eta first
+ * with zeta's held, then zeta (synchronises the stream; the blocks'
+ * workspaces are overwritten, q is not).  The choice is kept for later
+ * fp_batch_set calls and cached per process, keyed by the scheme and a size
+ * class of the batch (its dimensionalities and, per dimensionality, the
+ * binary orders of magnitude of its node count and mean eta and zeta line
+ * lengths): a later call on a batch of the same class reuses it without
+ * timing.  The eta target is written to *segment if non-NULL. */
 fp_status fp_batch_autotune(fp_batch *batch, int32_t *segment, void *stream);
+
+/* The batch's current segment-length targets, and whether the last
+ * fp_batch_autotune took them from its cache (1) or timed them (0).  NULL
+ * outputs are skipped. */
+fp_status fp_batch_get_tiles(const fp_batch *batch, int32_t *seg_eta, int32_t *seg_zeta,
+                             int32_t *from_cache);
 
 /* Instrumented step: one RK3 step of every block, exactly as
  * fp_batch_rk3_step, with a HIP event recorded on `stream` after each of its

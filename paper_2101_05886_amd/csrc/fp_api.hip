@@ -3,6 +3,9 @@
 // cache of fp_solve.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -482,7 +485,7 @@ struct fp_batch {
     fp_scheme sch{};
     SchemeK sk{};
     int cap = 0;
-    int seg = kSegDefault;  // eta / zeta segment length target
+    int seg[3] = {0, kSegDefault, kSegDefault};  // eta / zeta segment length targets
     size_t part_bytes = 0;  // one part's tables: [nblk | start | blocks]
     char* dmem = nullptr;   // device tables, part 0 = 2D blocks, part 1 = 3D blocks
     char* hstage = nullptr; // pinned host image of dmem
@@ -502,12 +505,57 @@ struct fp_batch {
     hipGraphExec_t graph[16] = {};
     int nlink[2] = {0, 0};  // links per part (no exchange launches without)
     hipStream_t cs = nullptr;
+    bool tuned_from_cache = false;  // the last autotune reused a cached choice
 };
 
 namespace {
 
+// The autotuner's choices, per process: keyed by the scheme (reconstruction,
+// precision, metric order) and a size class of the batch (which
+// dimensionalities it holds, and per dimensionality the binary orders of
+// magnitude of its node count and of its mean line lengths along eta and
+// zeta).
+struct TuneKey {
+    int recon, prec, Y, mask;
+    int cls[2][3];
+    bool operator<(const TuneKey& o) const { return std::memcmp(this, &o, sizeof(TuneKey)) < 0; }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+int ilog2(double x) { return x >= 1.0 ? (int)std::floor(std::log2(x)) : 0; }
+
+TuneKey tune_key(const fp_batch* b) {
+    TuneKey k;
+    std::memset(&k, 0, sizeof k);
+    k.recon = b->sch.recon;
+    k.prec = b->sch.precision;
+    k.Y = b->sch.metric_order;
+    k.mask = (b->nblk[0] > 0 ? 1 : 0) | (b->nblk[1] > 0 ? 2 : 0);
+    for (int p = 0; p < 2; ++p) {
+        double nodes = 0.0, ne = 0.0, nz = 0.0;
+        int cnt = 0;
+        for (const fp_block& fb : b->blocks) {
+            if (fb.grid.ndim != (p == 0 ? 2 : 3)) continue;
+            nodes += (double)fb.grid.n[0] * fb.grid.n[1] * (fb.grid.ndim == 3 ? fb.grid.n[2] : 1);
+            ne += fb.grid.n[1];
+            nz += fb.grid.ndim == 3 ? fb.grid.n[2] : 0;
+            ++cnt;
+        }
+        if (cnt == 0) continue;
+        k.cls[p][0] = ilog2(nodes);
+        k.cls[p][1] = ilog2(ne / cnt);
+        k.cls[p][2] = ilog2(nz / cnt);
+    }
+    return k;
+}
+
+// part layout: [nblk | 256 B][start: BK_KINDS x (cap + 1) longs, then the
+// kinds' block orders: BK_KINDS x cap ints][blocks: cap][links ...]
 size_t start_offset() { return 256; }
-size_t blk_offset(int cap) { return 256 + align256(sizeof(long) * BK_KINDS * (size_t)(cap + 1)); }
+size_t blk_offset(int cap) {
+    return 256 + align256(sizeof(long) * BK_KINDS * (size_t)(cap + 1) + sizeof(int) * BK_KINDS * (size_t)cap);
+}
 // link region of a part: [nlink | 256 B][lstart: maxl + 1 longs][links: maxl]
 size_t lnk_offset(int cap) { return align256(blk_offset(cap) + sizeof(BBlock) * (size_t)cap); }
 size_t lnk_start_offset(int cap) { return lnk_offset(cap) + 256; }
@@ -536,9 +584,10 @@ void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, const 
         char* base = img + p * b->part_bytes;
         long* start = reinterpret_cast<long*>(base + start_offset());
         BBlock* blk = reinterpret_cast<BBlock*>(base + blk_offset(b->cap));
+        int* ord = reinterpret_cast<int*>(start + BK_KINDS * (b->cap + 1));
         const int ndim = p == 0 ? 2 : 3;
         int n = 0;
-        long acc[BK_KINDS] = {0, 0, 0, 0};
+        std::vector<std::array<long, BK_KINDS>> nitems;
         for (const fp_block& fb : blocks) {
             if (fb.grid.ndim != ndim) continue;
             BBlock& B = blk[n];
@@ -552,8 +601,8 @@ void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, const 
             B.R = fb.work + 2 * se;
             B.dt = fb.dt;
             B.S[0] = 0;
-            B.S[1] = seg_len(B.G.n[1], b->seg);
-            B.S[2] = ndim == 3 ? seg_len(B.G.n[2], b->seg) : 0;
+            B.S[1] = seg_len(B.G.n[1], b->seg[1]);
+            B.S[2] = ndim == 3 ? seg_len(B.G.n[2], b->seg[2]) : 0;
             bool frozen = false;
             for (int d = 0; d < ndim; ++d) frozen = frozen || fb.grid.bc[d] == FP_BC_FROZEN;
             long items[BK_KINDS];
@@ -561,13 +610,29 @@ void build_tables(const fp_batch* b, const std::vector<fp_block>& blocks, const 
             items[BK_ETA] = sweep_wg_items(B.G.n, 1, B.S[1]);
             items[BK_ZETA] = ndim == 3 ? sweep_wg_items(B.G.n, 2, B.S[2]) : 0;
             items[BK_GHOST] = frozen ? (frozen_slab_nodes(B.G, ndim) + 255) / 256 : 0;
-            for (int k = 0; k < BK_KINDS; ++k) {
-                start[k * (b->cap + 1) + n] = acc[k];
-                acc[k] += items[k];
-            }
+            nitems.push_back({items[0], items[1], items[2], items[3]});
             ++n;
         }
-        for (int k = 0; k < BK_KINDS; ++k) start[k * (b->cap + 1) + n] = acc[k];
+        // Work lists.  Items go to workgroups cyclically, so the eta / zeta
+        // lists put the blocks with the most iterations per item (longest
+        // segments) first: every round of items then has similar lengths and
+        // the workgroups finish together.  The xi and ghost items are of one
+        // size: block order.
+        for (int k = 0; k < BK_KINDS; ++k) {
+            std::vector<int> o(n);
+            for (int i = 0; i < n; ++i) o[i] = i;
+            if (k == BK_ETA || k == BK_ZETA) {
+                const int d = k == BK_ETA ? 1 : 2;
+                std::stable_sort(o.begin(), o.end(), [&](int a, int c) { return blk[a].S[d] > blk[c].S[d]; });
+            }
+            long acc = 0;
+            for (int i = 0; i < n; ++i) {
+                ord[k * b->cap + i] = o[i];
+                start[k * (b->cap + 1) + i] = acc;
+                acc += nitems[o[i]][k];
+            }
+            start[k * (b->cap + 1) + n] = acc;
+        }
         *reinterpret_cast<int*>(base) = n;
         nblk[p] = n;
         // the part's links, with block indices local to the part
@@ -1306,19 +1371,31 @@ fp_status fp_batch_autotune(fp_batch* b, int32_t* segment, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const int mask = batch_mask(b);
     if (mask == 0) {
-        if (segment) *segment = b->seg;
+        if (segment) *segment = b->seg[1];
         return FP_OK;
+    }
+    const TuneKey key = tune_key(b);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            b->seg[1] = it->second.first;
+            b->seg[2] = it->second.second;
+            b->tuned_from_cache = true;
+            st = upload_tables(b, b->blocks, b->links, s);
+            if (st) return st;
+            if (segment) *segment = b->seg[1];
+            return FP_OK;
+        }
     }
     hipEvent_t e0, e1;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    int best = b->seg;
-    float best_ms = -1.0f;
-    for (int T : kSegTargets) {
-        b->seg = T;
-        st = upload_tables(b, b->blocks, b->links, s);
-        if (st) break;
+    // time RK stage 1 (every sweep) of the current blocks for a choice
+    auto time_stage = [&](float* out) -> fp_status {
+        fp_status r = upload_tables(b, b->blocks, b->links, s);
+        if (r) return r;
         float ms = 0.0f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
             e = hipEventRecord(e0, s);
@@ -1330,20 +1407,46 @@ fp_status fp_batch_autotune(fp_batch* b, int32_t* segment, void* stream) {
             if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
             if (rep > 0) ms += t;  // the first repetition warms up
         }
-        if (e != hipSuccess) break;
-        if (best_ms < 0.0f || ms < best_ms) {
-            best_ms = ms;
-            best = T;
+        *out = ms;
+        return FP_OK;
+    };
+    // coordinate search: the eta target with zeta's held, then zeta's (2D
+    // blocks have no zeta sweep: their time does not depend on it)
+    for (int d = 1; d <= 2 && st == FP_OK && e == hipSuccess; ++d) {
+        int best = b->seg[d];
+        float best_ms = -1.0f;
+        for (int T : kSegTargets) {
+            b->seg[d] = T;
+            float ms = 0.0f;
+            st = time_stage(&ms);
+            if (st || e != hipSuccess) break;
+            if (best_ms < 0.0f || ms < best_ms) {
+                best_ms = ms;
+                best = T;
+            }
         }
+        b->seg[d] = best;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (st) return st;
     if (e != hipSuccess) return hip_fail(e, "fp_batch_autotune");
-    b->seg = best;
     st = upload_tables(b, b->blocks, b->links, s);
     if (st) return st;
-    if (segment) *segment = best;
+    b->tuned_from_cache = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = {b->seg[1], b->seg[2]};
+    }
+    if (segment) *segment = b->seg[1];
+    return FP_OK;
+}
+
+fp_status fp_batch_get_tiles(const fp_batch* b, int32_t* seg_eta, int32_t* seg_zeta, int32_t* from_cache) {
+    if (!b) return fail(FP_EINVAL, "batch is NULL");
+    if (seg_eta) *seg_eta = b->seg[1];
+    if (seg_zeta) *seg_zeta = b->seg[2];
+    if (from_cache) *from_cache = b->tuned_from_cache ? 1 : 0;
     return FP_OK;
 }
 

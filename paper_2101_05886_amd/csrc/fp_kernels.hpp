@@ -839,6 +839,15 @@ struct BTab {
     int cap;
 };
 
+// The order of the blocks within a kind's work list: position n of kind k
+// holds block kind_order(...)[n] (the list of a kind may put its blocks in
+// any order; the eta / zeta lists put the blocks with the longest items
+// first, so that the cyclic assignment of items to workgroups balances).
+// The array follows the prefix sums in the same table.
+__device__ __forceinline__ const int* kind_order(const long* t_start, int cap, int kind) {
+    return reinterpret_cast<const int*>(t_start + BK_KINDS * (cap + 1)) + kind * cap;
+}
+
 // Block of `item` at or after block b, for items that only increase.
 __device__ __forceinline__ int advance_block(const long* st, int nblk, int b, long item) {
     while (b + 1 < nblk && st[b + 1] <= item) ++b;
@@ -895,13 +904,14 @@ __global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void kb_sweep_x
     const int nblk = *t_nblk;
     const long* __restrict__ st = t_start + BK_X * (cap + 1);
     const long total = st[nblk];
+    const int* __restrict__ ord = kind_order(t_start, cap, BK_X);
     const long nw = (long)gridDim.x * 4;
     long item = (long)blockIdx.x * 4 + wave_id();
     int cur = 0;
     int b = 0;
     if (item < total) {
         b = find_block(st, nblk, item);
-        const BBlock& B = t_blk[b];
+        const BBlock& B = t_blk[ord[b]];
         x_stage<DIM, NE>(B.G, B.met, stage_in(B, stage), item - st[b], x_window(B.G.n[0], NE), L.b[0]);
     }
     for (; item < total; item += nw, cur ^= 1) {
@@ -910,11 +920,11 @@ __global__ __launch_bounds__(256) FP_XSWEEP_ATTR(PREC, RECON, Y) void kb_sweep_x
         int bn = b;
         if (item + nw < total) {
             bn = advance_block(st, nblk, b, item + nw);
-            const BBlock& N = t_blk[bn];
+            const BBlock& N = t_blk[ord[bn]];
             x_stage<DIM, NE>(N.G, N.met, stage_in(N, stage), item + nw - st[bn], x_window(N.G.n[0], NE),
                              L.b[cur ^ 1]);
         }
-        const BBlock& B = t_blk[b];
+        const BBlock& B = t_blk[ord[b]];
         const EpiK ep = stage_epi(B, stage, EPI_FIRST, DIM);
         x_compute<DIM, RECON, Y, PREC, false>(B.G, sk, ep, item - st[b], x_window(B.G.n[0], NE), L.b[cur]);
         b = bn;
@@ -934,10 +944,11 @@ __global__ __launch_bounds__(256) FP_SWEEP_ATTR void kb_sweep_wg(const int* __re
     const int nblk = *t_nblk;
     const long* __restrict__ st = t_start + KIND * (cap + 1);
     const long total = st[nblk];
+    const int* __restrict__ ord = kind_order(t_start, cap, KIND);
     int b = blockIdx.x < total ? find_block(st, nblk, blockIdx.x) : 0;
     for (long item = blockIdx.x; item < total; item += gridDim.x) {
         b = advance_block(st, nblk, b, item);
-        const BBlock& B = t_blk[b];
+        const BBlock& B = t_blk[ord[b]];
         const EpiK ep = stage_epi(B, stage, MODE, DIM);
         sweep_wg_item<DIM, DIR, RECON, Y, PREC>(B.G, sk, B.met, stage_in(B, stage), ep, B.S[DIR],
                                                 item - st[b], lds);

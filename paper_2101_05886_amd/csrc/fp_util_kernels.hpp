@@ -207,10 +207,11 @@ __global__ __launch_bounds__(256) void kb_frozen_ghosts(const int* __restrict__ 
     const int nblk = *t_nblk;
     const long* __restrict__ st = t_start + BK_GHOST * (cap + 1);
     const long total = st[nblk];
+    const int* __restrict__ ord = kind_order(t_start, cap, BK_GHOST);
     int b = blockIdx.x < total ? find_block(st, nblk, blockIdx.x) : 0;
     for (long item = blockIdx.x; item < total; item += gridDim.x) {
         b = advance_block(st, nblk, b, item);
-        const BBlock& B = t_blk[b];
+        const BBlock& B = t_blk[ord[b]];
         const long node = (item - st[b]) * 256 + threadIdx.x;
         if (node < frozen_slab_nodes(B.G, ndim))
             frozen_ghost_node(B.G, ndim, ndim + 2, B.q, B.A, B.B, node);

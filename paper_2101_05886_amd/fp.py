@@ -26,7 +26,7 @@ EXPORTS = ["fp_state_bytes", "fp_metric_bytes", "fp_coord_bytes", "fp_work_bytes
            "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step", "fp_rk3_step_noalloc", "fp_solve",
            "fp_max_dt",
            "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step", "fp_batch_solve",
-           "fp_batch_set_links", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error",
+           "fp_batch_set_links", "fp_batch_autotune", "fp_batch_get_tiles", "fp_batch_profile_step", "fp_batch_destroy", "fp_release_cache", "fp_last_error",
            "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_work_bytes", "fp_viscous_residual", "fp_solve_ns",
            "fp_profile_step"]
 
@@ -103,6 +103,7 @@ def lib():
         L.fp_batch_set_links.argtypes = [bp, C.POINTER(FPLink), C.c_int32, vp]
         L.fp_batch_solve.argtypes = [bp, C.c_int64, vp]
         L.fp_batch_autotune.argtypes = [bp, C.POINTER(C.c_int32), vp]
+        L.fp_batch_get_tiles.argtypes = [bp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.fp_batch_profile_step.argtypes = [bp, C.POINTER(C.c_float), C.POINTER(C.c_int32), C.c_int32,
                                             C.POINTER(C.c_int32), vp]
         L.fp_batch_destroy.argtypes = [bp]
@@ -113,7 +114,8 @@ def lib():
         for name in ("fp_metrics", "fp_face_fluxes", "fp_residual", "fp_residual_dir", "fp_rk3_step",
                      "fp_rk3_step_noalloc", "fp_solve",
                      "fp_max_dt", "fp_check_state", "fp_batch_create", "fp_batch_set", "fp_batch_rk3_step",
-                     "fp_batch_solve", "fp_batch_autotune", "fp_batch_profile_step", "fp_batch_set_links",
+                     "fp_batch_solve", "fp_batch_autotune", "fp_batch_get_tiles", "fp_batch_profile_step",
+                     "fp_batch_set_links",
                      "fp_apply_bcs", "fp_solve_bcs", "fp_viscous_residual", "fp_solve_ns", "fp_profile_step"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -479,9 +481,17 @@ class Batch:
         _check(lib().fp_batch_solve(self._h, int(nsteps), _stream()))
 
     def autotune(self) -> int:
+        """tune the eta and zeta segment targets; returns the eta target"""
         seg = C.c_int32(0)
         _check(lib().fp_batch_autotune(self._h, C.byref(seg), _stream()))
         return int(seg.value)
+
+    def tiles(self) -> dict:
+        """the current segment targets and whether the last autotune reused
+        the process-wide cache"""
+        e, z, c = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _check(lib().fp_batch_get_tiles(self._h, C.byref(e), C.byref(z), C.byref(c)))
+        return {"seg_eta": int(e.value), "seg_zeta": int(z.value), "from_cache": bool(c.value)}
 
     def profile_step(self):
         """One RK3 step with per-launch HIP-event timing: [(ndim, kind, ms)]

@@ -96,6 +96,7 @@ def test_batch_arguments_rejected_without_a_device():
     assert L.fp_batch_rk3_step(None, None) == fp.FP_EINVAL
     assert L.fp_batch_solve(None, 1, None) == fp.FP_EINVAL
     assert L.fp_batch_autotune(None, None, None) == fp.FP_EINVAL
+    assert L.fp_batch_get_tiles(None, None, None, None) == fp.FP_EINVAL
     L.fp_batch_destroy(None)
 
 

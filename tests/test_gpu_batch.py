@@ -134,14 +134,29 @@ def test_batch_autotune_keeps_results():
     b = fp.Batch(sc, 8)
     b.set([k.entry() for k in blocks])
     seg = b.autotune()
-    assert seg in (15, 23, 31, 47, 63, 95, 127)
+    targets = (15, 23, 31, 47, 63, 95, 127)
+    tiles = b.tiles()
+    assert seg == tiles["seg_eta"] and seg in targets and tiles["seg_zeta"] in targets
     for k in blocks:
         assert torch.equal(k.q, k.q0), "the autotuner must not touch q"
     b.solve(2)
     torch.cuda.synchronize()
     for i, k in enumerate(blocks):
         assert torch.equal(k.q, k.alone(sc, 2)), f"block {i} after autotune"
+    # a second batch of the same size class reuses the cached choice
+    for k in blocks:
+        k.q.copy_(k.q0)
+    b2 = fp.Batch(sc, 8)
+    b2.set([k.entry() for k in blocks])
+    b2.autotune()
+    t2 = b2.tiles()
+    assert t2["from_cache"] and (t2["seg_eta"], t2["seg_zeta"]) == (tiles["seg_eta"], tiles["seg_zeta"])
+    b2.solve(1)
+    torch.cuda.synchronize()
+    for i, k in enumerate(blocks):
+        assert torch.equal(k.q, k.alone(sc, 1)), f"block {i} after the cached autotune"
     b.close()
+    b2.close()
 
 
 def test_batch_rejects_bad_blocks():
