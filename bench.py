@@ -277,18 +277,34 @@ def cpu_baseline(w, xyz, q, g, budget_s=20.0):
         return steps, time.perf_counter() - t0
 
     threads = O.num_threads()
+    progress(f"cpu baseline: {threads} threads")
     steps, el = timed(budget_s * 0.5)
     out = {"value": nodes * 3 * steps / el, "unit": "cell-stage updates/s", "cores": threads,
            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
            "sample": f"{steps} full RK3 step(s) of the same {w['n']}^{w['ndim']} grid and state, "
                      f"FP64 oracle (gcc -O2, OpenMP over grid lines, {threads} threads), {el:.1f} s{note}"}
+    # one thread: the same recipe on a grid small enough that one step
+    # takes about budget_s / 4 at the per-node cost just measured, taken as
+    # if the threads had scaled perfectly (so the sample is never longer)
+    per_node = el / (steps * nodes) * threads
+    n1 = int((budget_s * 0.25 / per_node) ** (1.0 / w["ndim"]))
+    n1 = max(16, min(w["n"], n1))
+    w1 = dict(w, n=n1)
+    xyz1, q1, g1 = make_inputs(w1)
+    og1 = O.Grid(w["ndim"], n1, g1)
+    met1 = O.metrics(og1, w["Y"], xyz1)
+    dt1 = O.max_dt(og1, sc, met1, q1, w["cfl"])
+    progress(f"cpu baseline: one thread, {n1}^{w['ndim']}")
     O.set_num_threads(1)
     try:
-        steps1, el1 = timed(budget_s * 0.25)
+        t0 = time.perf_counter()
+        O.rk3_step(og1, sc, met1, q1, dt1)
+        el1 = time.perf_counter() - t0
     finally:
         O.set_num_threads(threads)
-    out["single_thread"] = {"value": nodes * 3 * steps1 / el1, "cores": 1,
-                            "sample": f"{steps1} full RK3 step(s), one thread, {el1:.1f} s"}
+    out["single_thread"] = {"value": n1 ** w["ndim"] * 3 / el1, "cores": 1,
+                            "sample": f"one full RK3 step of the same recipe at {n1}^{w['ndim']}, one thread, "
+                                      f"{el1:.1f} s"}
     return out
 
 
@@ -341,12 +357,14 @@ def cpu_baseline_blocks(w, blocks, g, budget_s=20.0):
         return nodes, used, el
 
     threads = O.num_threads()
+    progress(f"cpu baseline: {threads} threads")
     nodes, used, el = timed(budget_s * 0.5)
     out = {"value": nodes * 3 / el, "unit": "cell-stage updates/s", "cores": threads, "kind": "oracle",
            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
            "sample": f"one RK3 step of each of the first {used} of the {len(blocks)} blocks "
                      f"({nodes} nodes), FP64 oracle (gcc -O2, OpenMP over grid lines, {threads} threads), "
                      f"{el:.1f} s"}
+    progress("cpu baseline: one thread")
     O.set_num_threads(1)
     try:
         nodes1, used1, el1 = timed(budget_s * 0.25)
@@ -429,13 +447,25 @@ def bench_dmr(args, w):
         ob = O.Bcs(f["kind"], mask=f["mask"], nodes=nodes, pre=f["pre"], post=f["post"], normal=f["normal"],
                    offset=f["offset"], speed=f["speed"])
         omet = O.metrics(og, Y, xyz)
+        osc = O.Scheme(w["recon"], Y, True, splitting="glf")
+        threads = O.num_threads()
         t0 = time.perf_counter()
-        O.solve_bcs(og, O.Scheme(w["recon"], Y, True, splitting="glf"), ob, omet, q, 0.0, dt, 2)
+        O.solve_bcs(og, osc, ob, omet, q, 0.0, dt, 2)
         el = time.perf_counter() - t0
+        O.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            O.solve_bcs(og, osc, ob, omet, q, 0.0, dt, 1)
+            el1 = time.perf_counter() - t0
+        finally:
+            O.set_num_threads(threads)
         out["cpu_baseline"] = {"value": nodes_n * 3 * 2 / el, "unit": "cell-stage updates/s",
-                               "cores": O.num_threads(), "kind": "oracle",
+                               "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+                               "nproc": os.cpu_count(),
                                "sample": f"2 RK3 steps of the same grid and state with its boundary faces, "
-                                         f"FP64 oracle, {el:.1f} s"}
+                                         f"FP64 oracle ({threads} threads), {el:.1f} s",
+                               "single_thread": {"value": nodes_n * 3 / el1, "cores": 1,
+                                                 "sample": f"one RK3 step, one thread, {el1:.1f} s"}}
     print(json.dumps(out), flush=True)
 
 
