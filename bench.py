@@ -42,10 +42,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
-# The ALU ceiling this build can reach, from the chip's unit counts: 256 CUs
+# The ALU ceiling the library can reach, from the chip's unit counts: 256 CUs
 # x 4 SIMDs x 16 lanes x 2 flop (fma) x 2.4 GHz = 78.6 TFLOP/s for FP64 and
 # for non-packed FP32 alike (the published 157.3 TFLOP/s FP32 needs packed
-# FP32 instructions, which this build disables).
+# FP32 instructions, which the library's compile flags disable).
 CU, SIMD_PER_CU, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
 PEAK_ALU_TFLOPS = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ / 1e12
 # VALU issue: one wave64 instruction occupies a SIMD for 4 cycles
@@ -181,7 +181,7 @@ WORKLOADS = {
     "c2": dict(name="3D isentropic vortex (strength 5, radius 1), 128^3 periodic wavy grid "
                     "(amplitude 0.1), linear-upwind-5 with 6th-order metrics, FP64",
                ndim=3, n=128, Y=6, recon="linup5", prec="fp64", L=12.0, amp=0.1, jitter=0.0,
-               seed=2, mach=0.5, vortex=True, cfl=0.5),
+               seed=2, mach=0.5, vortex=True, cfl=0.5, convergence=(32, 64)),
     "c3": dict(name="3D 256^3 periodic wavy grid (amplitude 0.1, 5% jitter), Mach 0.8 + vortex, "
                     "WENO5-JS with 6th-order metrics, FP64",
                ndim=3, n=256, Y=6, recon="weno5", prec="fp64", L=12.0, amp=0.1, jitter=0.05,
@@ -305,7 +305,38 @@ def cpu_baseline(w, xyz, q, g, budget_s=20.0):
     out["single_thread"] = {"value": n1 ** w["ndim"] * 3 / el1, "cores": 1,
                             "sample": f"one full RK3 step of the same recipe at {n1}^{w['ndim']}, one thread, "
                                       f"{el1:.1f} s"}
+    if "convergence" in w:
+        out["convergence_runs"] = cpu_convergence_runs(w, sc, threads)
     return out
+
+
+def cpu_convergence_runs(w, sc, threads):
+    """The oracle over whole convergence runs of the workload's recipe (t = 0
+    to 1, dt = dt_32 (32/n)^(5/3) with dt_32 the CFL step of the coarsest
+    grid): the coarsest grid with all threads and with one, the next with
+    all threads."""
+    import oracle as O
+    runs, dt32 = [], None
+    n0, n1 = w["convergence"]
+    for n, nt in ((n0, threads), (n0, 1), (n1, threads)):
+        wn = dict(w, n=n)
+        xyz, q, g = make_inputs(wn)
+        og = O.Grid(w["ndim"], n, g)
+        met = O.metrics(og, w["Y"], xyz)
+        if dt32 is None:
+            dt32 = O.max_dt(og, sc, met, q, w["cfl"])
+        steps = math.ceil(1.0 / (dt32 * (n0 / n) ** (5.0 / 3.0)))
+        progress(f"cpu baseline: convergence run {n}^{w['ndim']}, {steps} steps, {nt} thread(s)")
+        O.set_num_threads(nt)
+        try:
+            t0 = time.perf_counter()
+            O.solve(og, sc, met, q, 1.0 / steps, steps)
+            el = time.perf_counter() - t0
+        finally:
+            O.set_num_threads(threads)
+        runs.append({"n": n, "steps": steps, "cores": nt, "seconds": el,
+                     "value": n ** w["ndim"] * 3 * steps / el, "unit": "cell-stage updates/s"})
+    return runs
 
 
 def nodes_of(w):
@@ -645,8 +676,8 @@ def bench_batch(args, w):
         "mixed_over_fp64": value / res["fp64"]["value"],
         "repeats": res["mixed"]["repeats"],
         "roofline": roof,
-        "hbm_stage": {"bytes_per_cell_stage": STAGE_BYTES[3], "achieved": stage_gbs,
-                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS},
+        "hbm_stage": with_copy({"bytes_per_cell_stage": STAGE_BYTES[3], "achieved": stage_gbs,
+                                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS}),
         "state_ok": res["mixed"]["ok"] and res["fp64"]["ok"],
     }
     if not args.no_serving:
@@ -741,6 +772,35 @@ def copy_calibration(torch):
     print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 5}), flush=True)
 
 
+def copy_bandwidth():
+    """Achievable HBM bandwidth on this GPU: a plain device copy of 1 GiB
+    (read + write), five launches timed with HIP events; the median."""
+    import torch
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    ms = sorted(times)[len(times) // 2]
+    return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
+
+
+def with_copy(hbm):
+    """hbm_stage plus the measured copy bandwidth it can be read against"""
+    gbs = copy_bandwidth()
+    hbm["copy_gbs"] = gbs
+    hbm["frac_of_copy"] = hbm["achieved"] / gbs
+    return hbm
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -762,7 +822,7 @@ def main():
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the design notes describe how the method would shard)", file=sys.stderr)
         sys.exit(2)
 
@@ -871,8 +931,8 @@ def main():
                    "recon": w["recon"], "precision": w["prec"], "dt": dt},
         "roofline": roof,
         "repeats": median_rate(reps, nodes * 3 * args.steps),
-        "hbm_stage": {"bytes_per_cell_stage": STAGE_BYTES[ndim], "achieved": stage_gbs,
-                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS},
+        "hbm_stage": with_copy({"bytes_per_cell_stage": STAGE_BYTES[ndim], "achieved": stage_gbs,
+                                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": stage_gbs / PEAK_HBM_GBS}),
         "wall_s": wall, "state_ok": healthy,
     }
     if mu > 0:

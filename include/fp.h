@@ -62,7 +62,8 @@ typedef enum {
     FP_EUNSUPPORTED = -2,  /* well-formed but not provided (e.g. metric order 3) */
     FP_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
     FP_ENOMEM = -4,        /* a setup entry point could not allocate */
-    FP_ENONPHYS = -5       /* reserved for state checks reported to the host */
+    FP_ENONPHYS = -5       /* reserved: no entry point returns it; non-physical
+                              states are reported by fp_check_state's device flag */
 } fp_status;
 
 /* Reconstruction of the characteristic split fluxes (Sec. 3 and Remark 2):
@@ -287,14 +288,21 @@ fp_status fp_profile_step(const fp_grid *grid, const fp_scheme *scheme, const fp
                           double dt, float *kernel_ms, int32_t *kernel_kind, int32_t max_kernels,
                           int32_t *n_kernels, void *stream);
 
-/* dt = cfl / max_i sum_d (|s_d . u| + c |s_d|) (1/J)^{-1} over the interior
- * (the convective CFL limit), written to dt_dev (device, one double). */
+/* dt = cfl / max_i sum_d (|s_d . u| + c |s_d|) (1/J)^{-1} over the interior,
+ * written to dt_dev (device, one double).  The test cases of Sec. 4 are run
+ * at a stated CFL number (Sec. 4.2.1: 0.6) without the rule being printed;
+ * this is the convective limit in index space, the characteristic speeds of
+ * the transformed equations of Sec. 2.1 (|U_d| + c |grad xi_d| along each
+ * index direction) summed over the directions.  FP_EINVAL on a bad grid,
+ * scheme or pointer; cfl must be positive. */
 fp_status fp_max_dt(const fp_grid *grid, const fp_scheme *scheme, const double *met,
                     const double *q, double cfl, double *dt_dev, void *stream);
 
 /* flag_dev (device int32) is set to 1 if any interior node has a non-finite
  * value, rho <= 0 or p <= 0; it is left unchanged otherwise (the caller
- * clears it). */
+ * clears it).  A diagnostic, not a step of the method: it detects the
+ * breakdown (negative density or pressure) that Sec. 4.2 reports for the
+ * standard schemes on randomized grids. */
 fp_status fp_check_state(const fp_grid *grid, const fp_scheme *scheme, const double *q,
                          int32_t *flag_dev, void *stream);
 
