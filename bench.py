@@ -68,6 +68,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 # VALU wave instructions per launch (SQ_INSTS_VALU) of the sweep kernels:
 # profiles/valu_insts.json.
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_insts.json")
+# Active shader cycles of each sweep launch (GRBM_GUI_ACTIVE counter runs):
+# profiles/active_cycles.json.
+CYCLES_FILE = os.path.join(ROOT, "profiles", "active_cycles.json")
 
 
 def alg_flops_per_face(recon, ndim, Y):
@@ -157,7 +160,29 @@ def roofline(recon, ndim, Y, prec, kernel, kernel_ms, faces, nodes, key):
                         "peak_gbs": PEAK_HBM_GBS, "frac": alg_bytes / t / 1e9 / PEAK_HBM_GBS},
             "traffic_gbs": traffic / t / 1e9 if traffic else None,
             "traffic_bytes_per_node": traffic / nodes if traffic else None,
-            "counted_flops_per_face": counted}
+            "counted_flops_per_face": counted,
+            "clock": clock_view(key, achieved, insts, t)}
+
+
+def clock_view(key, achieved, insts, t):
+    """The same launch against the shader clock it ran at: VALU-bound
+    launches run below the 2.4 GHz peak clock (power management), so the
+    ALU ceiling they can reach is peak x clock / 2.4 GHz.  The launch's
+    active cycles come from a separate GRBM_GUI_ACTIVE counter run
+    (profiles/active_cycles.json; none for launches too short to measure);
+    the clock of the live launch is those cycles over its live duration,
+    and the VALU issue per active cycle is SQ_INSTS_VALU x 4 over (1,024
+    SIMDs x the cycles), independent of either run's duration."""
+    ctab, ccur = counter_table(CYCLES_FILE)
+    rec = ctab.get(key) if ccur else None
+    if not rec:
+        return None
+    cyc = rec["active_cycles"]
+    ghz = cyc / t / 1e9
+    scale = ghz * 1e9 / CLOCK_HZ
+    return {"active_cycles": cyc, "live_ghz": ghz, "counter_run_ghz": rec["ghz"],
+            "alu_peak_at_clock": PEAK_ALU_TFLOPS * scale, "frac_at_clock": achieved / (PEAK_ALU_TFLOPS * scale),
+            "valu_issue_per_cycle": insts * 4.0 / (CU * SIMD_PER_CU * cyc) if insts else None}
 
 
 def cpu_model():
