@@ -11,6 +11,9 @@ benchmark times.
   the coordinates (the oracle uses no GPU output); WENOCU6 also in the
   FP32-mixed form its benchmark times (bar 1e-4 of the sampled residual's
   largest value per variable, as for the mixed residual at small sizes).
+* The same grid and state with WENO7-JS and eighth-order metrics (ghost 4)
+  and with WENOCU6: one full RK3 step at every node from identical inputs,
+  FP64 and the FP32-mixed form their benchmarks time.
 * The same grid and state with the sixth-order viscous fluxes (mu 1e-3,
   Prandtl 0.72): the Navier-Stokes residual at every interior node against
   the oracle's, both from the oracle's metrics (bars as at small sizes).
@@ -201,6 +204,40 @@ def test_c3_256_full_rk3_step_same_inputs():
     diff = (interior(got, g, 3) - interior(ref, g, 3)).reshape(5, -1)
     rel = [float(np.abs(diff[v]).max() / np.abs(inc[v]).max()) for v in range(5)]
     print(f"C3 256^3 mixed step vs FP64 oracle, per variable, of the increment: {rel}", flush=True)
+    assert max(rel) <= 1e-4
+
+
+@pytest.mark.parametrize("recon,Y,g", [("weno7", 8, 4), ("wenocu6", 6, 3)])
+def test_c3_256_wide_and_cu6_full_rk3_step_same_inputs(recon, Y, g):
+    """The benchmarked 256^3 blocks of WENO7-JS with eighth-order metrics
+    (ghost 4) and WENOCU6 with sixth-order metrics: one RK3 step at every
+    node from identical inputs, FP64 within 1e-12 per variable of the
+    oracle and the FP32-mixed form the benchmark times within 1e-4 of the
+    step's increment."""
+    n = 256
+    xyz, q = c3_grid_and_state(n, g, Y)
+    og, fg = O.Grid(3, n, g), fp.Grid(3, n, g)
+    met = O.metrics(og, Y, xyz)
+    del xyz
+    osc = O.Scheme(recon, Y, True)
+    dt = O.max_dt(og, osc, met, q, 0.5)
+    print(f"C3 256^3 {recon}-M{Y}, one RK3 step, dt {dt:.4e}", flush=True)
+    ref = O.rk3_step(og, osc, met, q, dt)
+    mg = dev(met)
+    del met
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    qg = dev(q)
+    fp.rk3_step(fg, fp.Scheme(recon, Y, True), mg, qg, work, dt)
+    err = relerr(interior(host(qg), g, 3), interior(ref, g, 3))
+    print(f"C3 256^3 {recon}-M{Y} FP64 step vs oracle: {err:.2e}", flush=True)
+    assert err <= 1e-12
+    qg.copy_(dev(q))
+    fp.rk3_step(fg, fp.Scheme(recon, Y, True, precision="mixed"), mg, qg, work, dt)
+    got = host(qg)
+    inc = (interior(ref, g, 3) - interior(q, g, 3)).reshape(5, -1)
+    diff = (interior(got, g, 3) - interior(ref, g, 3)).reshape(5, -1)
+    rel = [float(np.abs(diff[v]).max() / np.abs(inc[v]).max()) for v in range(5)]
+    print(f"C3 256^3 {recon}-M{Y} mixed step vs FP64 oracle, of the increment: {rel}", flush=True)
     assert max(rel) <= 1e-4
 
 
