@@ -196,6 +196,40 @@ def test_solve_bcs_matches_the_oracle():
                 assert relerr(interior(host(qg), g, 2), interior(ref, g, 2)) <= 1e-11, (recon, split)
 
 
+@pytest.mark.parametrize("rand", [0.05, 0.2])
+def test_double_mach_reflection_full_size_steps_match_the_oracle(rand):
+    """The benchmarked double Mach reflection (961 x 241, WENO5-M6, global
+    LF, boundary faces every stage, dt at CFL 0.6 from the initial state)
+    through the captured step graph of fp_solve_bcs: 20 steps against the
+    oracle's, at the bar of the small boundary-driven runs."""
+    og, fg, met, q, nodes, ob, fb = dmr_case(961, 241, rand)
+    osc = O.Scheme("weno5", 6, True, splitting="glf")
+    fsc = fp.Scheme("weno5", 6, True, splitting="glf")
+    dt = O.max_dt(og, osc, met, q, 0.6)
+    ref = O.solve_bcs(og, osc, ob, met, q, 0.0, dt, 20)
+    qg = dev(q)
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    fp.solve_bcs(fg, fsc, fb, dev(met), qg, work, 0.0, dt, 20)
+    err = relerr(interior(host(qg), 3, 2), interior(ref, 3, 2))
+    print(f"DMR {rand:.0%} grid, 20 steps at dt {dt:.4e}: {err:.2e} of the oracle", flush=True)
+    assert err <= 1e-11
+
+
+def test_supersonic_cylinder_full_size_steps_match_the_oracle():
+    """The 61 x 81 cylinder grid with 20% randomness at its full size and
+    dt = 0.005: 20 steps of fp_solve_bcs against the oracle's."""
+    og, fg, met, q, nodes, ob, fb = cylinder_case(61, 81, 0.2)
+    osc = O.Scheme("weno5", 6, True, splitting="glf")
+    fsc = fp.Scheme("weno5", 6, True, splitting="glf")
+    ref = O.solve_bcs(og, osc, ob, met, q, 0.0, 0.005, 20)
+    qg = dev(q)
+    work = torch.zeros(fg.work_shape(), dtype=torch.float64, device="cuda")
+    fp.solve_bcs(fg, fsc, fb, dev(met), qg, work, 0.0, 0.005, 20)
+    err = relerr(interior(host(qg), 3, 2), interior(ref, 3, 2))
+    print(f"cylinder, 20 steps: {err:.2e} of the oracle", flush=True)
+    assert err <= 1e-11
+
+
 def prim(q):
     rho = q[0]
     u, v = q[1] / rho, q[2] / rho
