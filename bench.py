@@ -453,9 +453,14 @@ def bench_dmr(args, w):
     qg = torch.from_numpy(q).to(dev)
     work = torch.zeros(G.work_shape(), dtype=torch.float64, device=dev)
     dt = float(fp.max_dt(G, S, met, qg, w["cfl"]).item())
-    fp.solve_bcs(G, S, bcs, met, qg, work, 0.0, dt, max(args.warmup, 1))
-    torch.cuda.synchronize()
-    t = max(args.warmup, 1) * dt
+    clock = {"t": 0.0}
+
+    def run_bcs(k):
+        fp.solve_bcs(G, S, bcs, met, qg, work, clock["t"], dt, k)
+        clock["t"] += k * dt
+
+    warmup = warm_up(run_bcs, args.warmup)
+    t = clock["t"]
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     fp.solve_bcs(G, S, bcs, met, qg, work, t, dt, args.steps)
@@ -488,7 +493,7 @@ def bench_dmr(args, w):
                  "sweeps_share_of_step": 3 * (kt[0] + kt[1]) / (ms_total / args.steps)})
     out = {
         "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_total / args.steps,
+        "n_gpus": 1, "steps": args.steps, "warmup": warmup, "ms_per_step": ms_total / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w["name"], "nodes": nodes_n, "metric_order": Y, "recon": w["recon"],
@@ -564,8 +569,7 @@ def bench_links(args, w):
     b.set_links(links)
     seg = b.autotune()
     tiles = b.tiles()
-    b.solve(max(args.warmup, 1))
-    torch.cuda.synchronize()
+    warmup = warm_up(b.solve, args.warmup)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     b.solve(args.steps)
@@ -598,7 +602,7 @@ def bench_links(args, w):
     halo_bytes = len(links) * g * sizes[0] * sizes[1] * 5 * 8 * 2
     out = {
         "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "n_gpus": 1, "steps": args.steps, "warmup": warmup, "ms_per_step": ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if w["prec"] == "fp64" else "f64 state, f32 reconstruction", "data": "synthetic",
         "config": {"workload": w["name"], "blocks": len(ent), "links": len(links), "nodes": nodes,
@@ -642,8 +646,7 @@ def bench_batch(args, w):
         b.set(ent)
         seg = b.autotune()
         tiles = b.tiles()
-        b.solve(max(args.warmup, 1))
-        torch.cuda.synchronize()
+        warmup = warm_up(b.solve, args.warmup)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         b.solve(args.steps)
@@ -668,7 +671,8 @@ def bench_batch(args, w):
             kinds.setdefault(kind, []).append(t)
         per_kernel[prec] = {k: sum(v) / len(v) for k, v in kinds.items()}
         res[prec] = dict(value=nodes * 3 * args.steps / (ms * 1e-3), ms_step=ms / args.steps, seg=seg,
-                         ok=flag_ok, repeats=median_rate(reps, nodes * 3 * args.steps), tiles=tiles)
+                         ok=flag_ok, repeats=median_rate(reps, nodes * 3 * args.steps), tiles=tiles,
+                         warmup=warmup)
         progress(f"batch {prec}: {res[prec]['value']:.3e} cell-stage/s (segment {seg})")
         b.close()
         del ent
@@ -689,13 +693,13 @@ def bench_batch(args, w):
     stage_gbs = STAGE_BYTES[3] * value / 1e9
     out = {
         "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["mixed"]["ms_step"],
+        "n_gpus": 1, "steps": args.steps, "warmup": res["mixed"]["warmup"], "ms_per_step": res["mixed"]["ms_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 state, f32 reconstruction", "data": "synthetic",
         "config": {"workload": w["name"], "blocks": len(blocks), "nodes": nodes, "metric_order": w["Y"],
                    "recon": w["recon"], "precision": "mixed", "segment": res["mixed"]["seg"],
                    "tiles": res["mixed"]["tiles"]},
-        "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_step"],
+        "fp64": {"value": res["fp64"]["value"], "ms_per_step": res["fp64"]["ms_step"], "warmup": res["fp64"]["warmup"],
                  "segment": res["fp64"]["seg"], "tiles": res["fp64"]["tiles"], "repeats": res["fp64"]["repeats"],
                  "roofline": roof64},
         "mixed_over_fp64": value / res["fp64"]["value"],
@@ -715,6 +719,32 @@ def bench_batch(args, w):
 
 def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+WARMUP_S = 0.3
+
+
+def warm_up(run, requested):
+    """Untimed steps before the timed region: `requested` of them, or (when
+    none is requested) at least three and about WARMUP_S seconds of them, so
+    that a workload of short steps starts its timed region with the GPU out
+    of its idle clocks.  run(k) enqueues k steps.  Returns the steps run."""
+    import torch
+    if requested is not None:
+        run(max(requested, 1))
+        torch.cuda.synchronize()
+        return requested
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run(3)
+    e1.record()
+    e1.synchronize()
+    per_step = max(e0.elapsed_time(e1) / 3, 1e-3) * 1e-3
+    extra = max(0, math.ceil(WARMUP_S / per_step) - 3)
+    if extra:
+        run(extra)
+    torch.cuda.synchronize()
+    return 3 + extra
 
 
 def serve_measure(w):
@@ -830,7 +860,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps before the timed region (default: at least 3 and about "
+                         f"{WARMUP_S} s of steps)")
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
@@ -895,8 +927,7 @@ def main():
         run = lambda k: fp.solve(G, S, met, qg, work, dt, k)  # noqa: E731
 
     # warmup (captures the step graph), then the timed region
-    run(max(args.warmup, 1))
-    torch.cuda.synchronize()
+    warmup = warm_up(run, args.warmup)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
@@ -948,7 +979,7 @@ def main():
     stage_gbs = STAGE_BYTES[ndim] * value / 1e9
     out = {
         "metric": "cell-stage updates/s", "value": value, "unit": "cell-stage updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "n_gpus": 1, "steps": args.steps, "warmup": warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if w["prec"] == "fp64" else "f64 state, f32 reconstruction",
         "data": "synthetic",
