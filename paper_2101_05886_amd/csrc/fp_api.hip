@@ -941,8 +941,10 @@ fp_status fp_solve(const fp_grid* g, const fp_scheme* sch, const double* met, do
     key.work = work;
     key.dt = dt;
     hipGraphExec_t exec = nullptr;
+    // held until the step graph's launches are enqueued: another thread may
+    // evict and destroy cached graphs (a full cache, fp_release_cache)
+    std::lock_guard<std::mutex> lk(g_mu);
     {
-        std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_graphs.find(key);
         if (it != g_graphs.end()) {
             exec = it->second;
@@ -1058,8 +1060,9 @@ fp_status fp_solve_bcs(const fp_grid* g, const fp_scheme* sch, const fp_bcs* bcs
     key.k.dt = dt;
     key.bc = k;
     hipGraphExec_t exec = nullptr;
+    // held until the step graph's launches are enqueued (as in fp_solve)
+    std::lock_guard<std::mutex> lk(g_mu);
     {
-        std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_bc_graphs.find(key);
         if (it != g_bc_graphs.end()) {
             exec = it->second;
