@@ -51,3 +51,16 @@ def sample_nodes(n, ndim, count, seed=0):
     for _ in range(count):
         pts.append([int(rng.integers(0, n[d])) for d in range(ndim)] + [0] * (3 - ndim))
     return np.array(pts, dtype=np.int32)
+
+
+def smooth_periodic_state(n, g, mach=0.5, eps=0.01, gamma=GAMMA):
+    """Uniform 3D flow (Mach `mach` along the 3D direction of the workloads,
+    p = 1) whose density carries the periodic perturbation
+    1 + eps*s(i)*s(j)*s(k), s(i) = sin(2*pi*(i + 1/2)/n) over the node index
+    (ghost nodes take their periodic image's value); the pressure stays 1.
+    Separable, so it is cheap at any size."""
+    idx = np.arange(-g, n + g) % n
+    s = np.sin(2.0 * math.pi * (idx + 0.5) / n)
+    rho = gamma * (1.0 + eps * s[:, None, None] * s[None, :, None] * s[None, None, :])
+    vel = I.mach_velocity(mach, I.direction_3d())
+    return np.ascontiguousarray(I.primitive_to_conserved(rho, [float(v) for v in vel], 1.0, gamma))
