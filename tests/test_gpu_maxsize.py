@@ -9,7 +9,7 @@ corners, i.e. the largest indices, and random interior nodes) against the
 oracle evaluated node by node from the coordinates, with the bars of the
 256^3 sampled test; and the residual of the uniform flow, which must vanish
 to round-off at every node (free-stream preservation at full size): within
-10 eps max|x|/h, the rounding of metrics that are differences of coordinate
+10 unit roundoffs of max|x|/h, the rounding of metrics that are differences of coordinate
 products."""
 import math
 
