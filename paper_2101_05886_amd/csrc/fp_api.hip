@@ -1395,12 +1395,14 @@ fp_status fp_batch_autotune(fp_batch* b, int32_t* segment, void* stream) {
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
-    // time RK stage 1 (every sweep) of the current blocks for a choice
+    // time RK stage 1 (every sweep) of the current blocks for a choice: the
+    // fastest of four repetitions after one that warms up (the optimum is
+    // flat, so a sum of few repetitions lets run-to-run noise pick)
     auto time_stage = [&](float* out) -> fp_status {
         fp_status r = upload_tables(b, b->blocks, b->links, s);
         if (r) return r;
-        float ms = 0.0f;
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        float ms = -1.0f;
+        for (int rep = 0; rep < 5 && e == hipSuccess; ++rep) {
             e = hipEventRecord(e0, s);
             for (int p = 0; p < 2 && e == hipSuccess; ++p)
                 if (mask & (1 << p)) e = b->fn[p](b->tab[p], b->sk, 0, b->grid[p], -1, s);
@@ -1408,7 +1410,7 @@ fp_status fp_batch_autotune(fp_batch* b, int32_t* segment, void* stream) {
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float t = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-            if (rep > 0) ms += t;  // the first repetition warms up
+            if (rep > 0 && (ms < 0.0f || t < ms)) ms = t;
         }
         *out = ms;
         return FP_OK;
