@@ -163,6 +163,10 @@ def test_cartesian_grid_matches_oracle_and_recovers_standard_scheme(ndim, n, h, 
     r0 = interior(host(fp.residual(fg, fp.Scheme(recon, Y, False), mg, qg)), g, ndim)
     # the residual bar: a difference of fluxes about 100 times larger
     assert np.abs(r1 - r0).max() <= 1e-11 * np.abs(r0).max()
+    # the FP32-mixed form: exactly tied normal components tie in FP32 too
+    rm = interior(host(fp.residual(fg, fp.Scheme(recon, Y, True, precision="mixed"), mg, qg)), g, ndim)
+    ro = interior(O.residual(og, osc, met, q), g, ndim)
+    assert relerr_vec(rm, ro, ndim) <= 1e-4
 
 
 # Short xi lines: the xi sweep packs the faces of consecutive lines into
