@@ -607,9 +607,14 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
 #pragma unroll
         for (int v = 0; v < NV; ++v) L.flux[w][v][lane] = F[v];
         __syncthreads();
+        // FP32-mixed: the stores go after the second barrier, so that its
+        // wait does not hold for their completion (they complete while the
+        // next face is computed); FP64 stores before it, as holding the
+        // epilogue operands across the barrier would spill its registers
+        constexpr bool late_store = sizeof(char_t<PREC>) == 4;
+        double d[NV];
         if (mine) {
             const double* prev = w > 0 ? &L.flux[w - 1][0][0] : &L.carry[0][0];
-            double d[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) d[v] = F[v] - prev[v * 64 + lane];
             if (own_qv && ep.mode >= EPI_LAST_RES) {
@@ -620,7 +625,7 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
 #pragma unroll
                 for (int v = 0; v < NV; ++v) pre.qin[v] = L.ring[slot][v][lane];
             }
-            epi_store<NV>(ep, G.vol, noff, pre, d);
+            if (!late_store) epi_store<NV>(ep, G.vol, noff, pre, d);
         }
         __builtin_amdgcn_s_waitcnt(0);  // this wave's row DMA has landed
         __syncthreads();                // every row of the next iteration is in LDS
@@ -630,6 +635,7 @@ __device__ __forceinline__ void sweep_wg_item(const GeoK& G, const SchemeK& sk,
 #pragma unroll
             for (int v = 0; v < NV; ++v) L.carry[v][lane] = F[v];
         }
+        if (late_store && mine) epi_store<NV>(ep, G.vol, noff, pre, d);
     }
 }
 
